@@ -1,0 +1,243 @@
+"""Benchmark of the sparse AA lattice Boltzmann step on one MI355X.
+
+Workload (default): D3Q19 TRT (Lambda = 3/16, tau = 0.8), AA in-place
+streaming, FP32 storage, body force F = 1e-6 x, on a 256^3 periodic box
+filled with seeded overlapping spheres (radius uniform 4-12) at porosity 0.6
+(synthetic stand-in for the paper's artificial porosity domains).
+
+One step = one AA half-step (odd or even kernel) over every fluid cell.
+`value` = fluid-cell updates per second (MFLUPS) over K timed steps with all
+data resident in HBM.  Per-kernel durations come from HIP events recorded on
+the launch stream between the launches of the timed region.
+
+Prints one JSON line.  `python bench.py --gpus N` with N > 1 exits: the
+build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MFLUPS + % HBM BW, sparse D3Q19 TRT 256^3 packing; p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def bytes_per_flup(q, b_pdf, b_idx=4):
+    """Algorithmic bytes per fluid-cell update (GPU access table of the
+    paper's AA section, generalised to the storage width)."""
+    odd = 2 * q * b_pdf + (q - 1) * b_idx
+    even = 2 * q * b_pdf
+    return odd, even, 0.5 * (odd + even)
+
+
+def copy_bandwidth(lbm, torch, nbytes=2 << 30, reps=10):
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        lbm.lbm_copy(dst, src, nbytes)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        lbm.lbm_copy(dst, src, nbytes)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    return 2 * nbytes / s / 1e9
+
+
+def cpu_baseline(lab, per, q, tau, magic, force, n_fluid, budget_s):
+    """The FP64 oracle (dense two-array pull, OpenMP over z-planes) on the
+    same geometry: one untimed step (first touch of the second array), then
+    whole-grid steps until `budget_s` seconds have passed."""
+    import ctypes
+
+    import numpy as np
+
+    import oracle
+    p = oracle.params(q=q, kind=oracle.TRT, tau=tau, magic=magic, force=force)
+    lib = oracle._load()
+    lab = np.ascontiguousarray(lab, np.uint8)
+    nz, ny, nx = lab.shape
+    A = oracle.dense_init(q, lab)
+    B = np.empty_like(A)
+
+    def step(a, b):
+        rc = lib.orc_dense_step(ctypes.byref(p), oracle._ptr(lab), nx, ny, nz, per,
+                                oracle._ptr(a), oracle._ptr(b))
+        if rc:
+            raise RuntimeError("oracle step failed")
+
+    step(A, B)
+    A, B = B, A
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        step(A, B)
+        A, B = B, A
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return {"value": round(n_fluid * steps / el / 1e6, 3), "unit": "MFLUPS",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{steps} dense FP64 pull TRT step(s) of the full {nx}x{ny}x{nz} geometry "
+                      f"({n_fluid} fluid cells) after one untimed step, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--phi", type=float, default=0.6)
+    ap.add_argument("--L", type=int, default=256)
+    ap.add_argument("--tau", type=float, default=0.8)
+    ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16dev", "bf16dev", "f32dev"])
+    ap.add_argument("--order", default="morton", choices=["morton", "lex"])
+    ap.add_argument("--dense-steps", type=int, default=200)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-copy", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus > 1 or world > 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2408_06880_amd import inputs, lbm
+
+    storage = {"f64": lbm.STORE_F64, "f32": lbm.STORE_F32, "f16dev": lbm.STORE_F16DEV,
+               "bf16dev": lbm.STORE_BF16DEV, "f32dev": lbm.STORE_F32DEV}[args.storage]
+    dev_exp = 14 if storage == lbm.STORE_F16DEV else 0
+    order = lbm.ORDER_MORTON if args.order == "morton" else lbm.ORDER_LEX
+    q, magic, force = 19, 3.0 / 16.0, (1e-6, 0.0, 0.0)
+    torch.cuda.set_device(0)
+
+    t0 = time.perf_counter()
+    lab, per, info = inputs.workload_c1(args.phi, L=args.L)
+    log(f"geometry {args.L}^3 phi={info['phi']:.4f} n_fluid={info['n_fluid']} "
+        f"({time.perf_counter() - t0:.1f} s)")
+    lab_dev = torch.from_numpy(lab).cuda()
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    dom = lbm.SparseDomain(lab_dev, per, q, order, 64)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - tb) * 1e3
+    nf = dom.n_fluid
+    sol = lbm.Solver(dom, storage, dev_exp)
+    coll = lbm.collision(lbm.COLL_TRT, tau=args.tau, magic=magic, force=force)
+    sol.init()
+    sol.step(args.warmup, coll)
+    torch.cuda.synchronize()
+    log(f"built lists in {build_ms:.1f} ms; warmup {args.warmup} steps done")
+
+    K = args.steps
+    stream = torch.cuda.current_stream()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+    parity0 = sol.t & 1
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    evs[0].record(stream)
+    for s in range(K):
+        lbm.lbm_step(sol.state, 1, coll, None, stream)
+        evs[s + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    durs = [evs[s].elapsed_time(evs[s + 1]) / 1e3 for s in range(K)]
+    odd_d = [d for s, d in enumerate(durs) if ((parity0 + s) & 1) == 0]
+    even_d = [d for s, d in enumerate(durs) if ((parity0 + s) & 1) == 1]
+    t_odd = sum(odd_d) / max(len(odd_d), 1)
+    t_even = sum(even_d) / max(len(even_d), 1)
+    mflups = nf * K / wall / 1e6
+    b_pdf = lbm.STORE_BYTES[storage]
+    b_odd, b_even, b_alg = bytes_per_flup(q, b_pdf)
+    log(f"timed {K} steps: {wall * 1e3:.2f} ms, {mflups:.0f} MFLUPS; odd {t_odd * 1e6:.1f} us, "
+        f"even {t_even * 1e6:.1f} us")
+    red = sol.reduce(coll)
+    if not red.finite:
+        raise RuntimeError("non-finite state after the timed steps")
+
+    copy_gbs = None if args.no_copy else copy_bandwidth(lbm, torch)
+    if copy_gbs:
+        log(f"copy kernel {copy_gbs:.0f} GB/s")
+
+    dense = None
+    if args.dense_steps > 0:
+        del sol
+        torch.cuda.empty_cache()
+        ds = lbm.DenseSolver(lab_dev, per, q, storage, dev_exp)
+        ds.init()
+        ds.step(10, coll)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ds.step(args.dense_steps, coll)
+        e1.record()
+        torch.cuda.synchronize()
+        sd = e0.elapsed_time(e1) / 1e3
+        dense = {"kernel": "dense direct-addressing AA over all cells",
+                 "mflups_fluid": nf * args.dense_steps / sd / 1e6,
+                 "mlups_all_cells": lab.size * args.dense_steps / sd / 1e6,
+                 "steps": args.dense_steps}
+        log(f"dense comparator {dense['mflups_fluid']:.0f} MFLUPS (fluid cells)")
+        del ds
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(lab, per, q, args.tau, magic, force, nf, args.cpu_seconds)
+        log(f"cpu oracle {cpu['value']:.1f} MFLUPS on {cpu['cores']} threads")
+
+    achieved = nf * b_odd / t_odd / 1e9
+    out = {
+        "metric": METRIC,
+        "value": round(mflups, 1),
+        "unit": "MFLUPS",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / K * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32", "f16dev": "f32 (f16 storage)",
+                  "bf16dev": "f32 (bf16 storage)", "f32dev": "f32"}[args.storage],
+        "data": "synthetic",
+        "config": {"workload": f"sparse D3Q19 TRT AA, {args.L}^3 periodic overlapping-sphere "
+                               f"packing phi={info['phi']:.3f} (r 4-12, seed {info['seed']})",
+                   "n_fluid": nf, "tau": args.tau, "magic": magic, "force": list(force),
+                   "storage": args.storage, "order": args.order, "stride": dom.stride},
+        "pct_hbm_peak": round(100.0 * mflups * 1e6 * b_alg / (HBM_PEAK_GBS * 1e9), 2),
+        "bytes_per_flup_alg": b_alg,
+        "roofline": {"bound": "hbm", "kernel": "AA odd step (index gather + collide + scatter)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": nf * b_odd, "avg_launch_us": round(t_odd * 1e6, 2)},
+        "even_kernel": {"achieved_gbs": round(nf * b_even / t_even / 1e9, 1),
+                        "avg_launch_us": round(t_even * 1e6, 2), "bytes_per_launch": nf * b_even},
+        "copy_kernel_gbs": round(copy_gbs, 1) if copy_gbs else None,
+        "pct_copy_bw": round(100.0 * mflups * 1e6 * b_alg / (copy_gbs * 1e9), 2) if copy_gbs else None,
+        "builder_ms": round(build_ms, 2),
+        "dense_comparator": dense,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

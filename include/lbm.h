@@ -1,0 +1,297 @@
+/*
+ * lbm.h -- C-ABI of the MI355X (gfx950) sparse, indirect-addressing lattice
+ * Boltzmann library (liblbm.so).
+ *
+ * The method is the sparse LBM of Suffa, Holzer, Koestler, Ruede,
+ * arXiv 2408.06880: PDFs of fluid cells only, stored as a structure-of-arrays
+ * "PDF-list"; neighbours reached through an int32 "index-list" with
+ * bounce-back and periodicity folded in (Section "Sparse Data Structure",
+ * "Sparse Boundary Conditions"); in-place AA streaming, alternating an
+ * "odd" step (pull, collide, push back to the read positions) and an "even"
+ * step (collide in place, opposite slots) so that one PDF array suffices
+ * (Section "In-place Streaming: AA Pattern").
+ *
+ * Conventions
+ *  - Every function returns lbm_status: LBM_OK (0) or a negative code.
+ *    On error, lbm_last_error() (per calling thread) holds a message.
+ *  - The caller owns all device memory and the HIP stream.  Pointers named
+ *    "device" must be device (HBM) allocations of at least the stated size;
+ *    "host" pointers are ordinary host memory.  `stream` is a hipStream_t
+ *    (NULL = the default stream).
+ *  - Calls are asynchronous on `stream` unless marked SYNC.  Kernel faults
+ *    surface at the next synchronising call as LBM_EDEVICE.
+ *  - No entry point allocates device memory.  Scratch comes in through a
+ *    caller-provided `workspace` whose size a *_workspace_bytes() query
+ *    returns.
+ *  - A given lbm_state must not be used from two threads at once; separate
+ *    states may be driven from different threads and streams.
+ *
+ * Lattice conventions (fixed; both the library and any reader of its
+ * buffers rely on them)
+ *  - Cell linear id: lin = x + nx*(y + ny*z).  Labels: uint8, 0 = fluid,
+ *    1 = solid (no-slip), 2 + c = boundary class c (c < 8).  Periodicity:
+ *    bit 0 = x, bit 1 = y, bit 2 = z.  A non-periodic box face is a no-slip
+ *    wall located halfway between the outermost cell layer and the outside.
+ *  - Directions: 0 = rest; then pairs (+e, -e): 1,2 = +-x; 3,4 = +-y;
+ *    5,6 = +-z; 7..18 = the xy, xz, yz edge pairs (+x+y,-x-y), (+x-y,-x+y),
+ *    (+x+z,-x-z), (+x-z,-x+z), (+y+z,-y-z), (+y-z,-y+z); D3Q27 adds the
+ *    corners 19..26: (+++,---), (++-,--+), (+-+,-+-), (-++,+--).  The
+ *    opposite of i >= 1 is i+1 for odd i and i-1 for even i.
+ *  - PDF-list: element i*S + k = population i of the k-th fluid cell
+ *    (S = stride >= n_fluid).  Index-list: element (i-1)*S + k = position
+ *    in the PDF-list that cell k pulls population i from.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lbm_status;
+
+#define LBM_OK 0
+#define LBM_EINVAL (-1)    /* invalid argument                                  */
+#define LBM_ERANGE (-2)    /* q * stride does not fit int32 positions            */
+#define LBM_ENOMEM (-3)    /* caller buffer / workspace too small                */
+#define LBM_EDEVICE (-4)   /* a HIP call failed                                  */
+#define LBM_EUNSTABLE (-5) /* a reduction saw NaN or Inf                          */
+#define LBM_ESTATE (-6)    /* layout / parity / storage mismatch between inputs   */
+
+enum { LBM_D3Q19 = 19, LBM_D3Q27 = 27 };
+enum { LBM_COLL_NONE = 0, LBM_COLL_SRT = 1, LBM_COLL_TRT = 2, LBM_COLL_CUMULANT = 3 };
+/* Storage of the PDF-list.  *DEV formats store the deviation f_i - w_i
+ * from the rest weights ("zero-centred" storage option, Section "Code
+ * Generation for Sparse Kernels"), 16-bit ones scaled by 2^dev_exp.  All
+ * arithmetic is FP32 except for LBM_STORE_F64, which computes in FP64. */
+enum {
+  LBM_STORE_F64 = 0,     /* double f_i                                            */
+  LBM_STORE_F32 = 1,     /* float f_i                                             */
+  LBM_STORE_F16DEV = 2,  /* IEEE half (f_i - w_i) * 2^dev_exp                     */
+  LBM_STORE_BF16DEV = 3, /* bfloat16 (f_i - w_i) * 2^dev_exp                      */
+  LBM_STORE_F32DEV = 4   /* float (f_i - w_i)                                     */
+};
+enum { LBM_ORDER_MORTON = 0, LBM_ORDER_LEX = 1 };
+enum { LBM_BC_NOSLIP = 0, LBM_BC_UBB = 1, LBM_BC_PRESSURE = 2 };
+
+/* Sizes of one sparse domain.  Filled by lbm_build_sparse (plan call). */
+typedef struct {
+  int32_t nx, ny, nz;
+  uint32_t periodic;
+  int32_t q;         /* 19 or 27                                               */
+  int32_t order;     /* LBM_ORDER_*                                            */
+  int32_t align;     /* stride is a multiple of align (1 = unpadded)           */
+  int32_t reserved;
+  int64_t n_fluid;   /* N_F                                                    */
+  int64_t stride;    /* S = round_up(N_F, align)                               */
+  int64_t n_links;   /* boundary links (upstream cell carries label >= 2)      */
+} lbm_layout;
+
+/* ------------------------------------------------------------------ */
+/* Builder: labels -> fluid list, index-list, boundary links.           */
+/* Section "Sparse Data Structure" (PDF-list, index-list; N_F*(Q-1)     */
+/* index entries since the rest population does not stream) and         */
+/* "Sparse Boundary Conditions" (no-slip pull index redirected to the   */
+/* same cell's opposite population; periodic pull index wrapped to the  */
+/* other side of the domain).                                           */
+/* ------------------------------------------------------------------ */
+
+/* Device workspace bytes lbm_build_sparse needs for an nx*ny*nz box.
+ * Host only; 0 for invalid sizes. */
+uint64_t lbm_build_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t order);
+
+/* Two-phase build.
+ *  labels     device, uint8[nx*ny*nz] (layout above); nx, ny, nz in [1, 1024].
+ *  order      LBM_ORDER_MORTON (fluid cells sorted by Morton key, bit b of
+ *             x, y, z at bits 3b, 3b+1, 3b+2) or LBM_ORDER_LEX (by lin).
+ *  align      stride multiple, >= 1 (64 recommended).
+ *  workspace  device, >= lbm_build_workspace_bytes(nx, ny, nz, order).
+ *  layout     host.  PLAN call (cells == NULL): SYNC; fills *layout; index
+ *             and links must be NULL.  FILL call (cells != NULL): *layout
+ *             must be the plan's result for the same labels (unchanged in
+ *             between); writes
+ *               cells  device int32[n_fluid]: lin of the k-th fluid cell;
+ *               index  device int32[(q-1)*stride]: element (i-1)*S + k =
+ *                      i*S + m if the upstream cell x_k - c_i (wrapped on
+ *                      periodic axes) is fluid with list position m, else
+ *                      opp(i)*S + k; padding k in [n_fluid, S) gets
+ *                      opp(i)*S + k (in bounds, never used);
+ *               links  device int32[2*n_links] (may be NULL iff n_links==0):
+ *                      pairs (opp(i)*S + k, i | class << 8) for every
+ *                      upstream cell with label 2 + class, ordered by (k, i).
+ * Errors: LBM_EINVAL (sizes, q, order, align), LBM_ERANGE (q*S >= 2^31),
+ *         LBM_EDEVICE. */
+lbm_status lbm_build_sparse(const uint8_t* labels, int32_t nx, int32_t ny, int32_t nz,
+                            uint32_t periodic, int32_t q, int32_t order, int32_t align,
+                            void* workspace, lbm_layout* layout, int32_t* cells, int32_t* index,
+                            int32_t* links, void* stream);
+
+/* ------------------------------------------------------------------ */
+/* State, collision parameters, boundary specification.                 */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+  lbm_layout layout;
+  int32_t storage;       /* LBM_STORE_*                                        */
+  int32_t dev_exp;       /* 16-bit formats: stored = (f - w) * 2^dev_exp, 0..24 */
+  void* pdf;             /* device, q*stride elements of the storage type      */
+  const int32_t* index;  /* device, (q-1)*stride (from lbm_build_sparse)       */
+  const int32_t* links;  /* device, 2*n_links or NULL when n_links == 0        */
+  int64_t t;             /* steps taken. t even: populations in natural slots  */
+} lbm_state;
+
+/* Collision operator (Section "Lattice Boltzmann Method" and "Code
+ * Generation for Sparse Kernels").  nu = (tau - 1/2)/3, tau > 1/2.
+ *  SRT:      relax all populations with omega = 1/tau (BGK).
+ *  TRT:      symmetric parts with omega+ = 1/tau, antisymmetric parts with
+ *            omega- from magic = (1/omega+ - 1/2)(1/omega- - 1/2).
+ *  CUMULANT: D3Q27 only; second-order shear/deviatoric moments relax with
+ *            1/tau, the trace with omega_bulk, all higher cumulants -> 0.
+ *  force:    constant body force density (Guo scheme, half-force velocity).
+ */
+typedef struct {
+  int32_t kind;          /* LBM_COLL_*                                         */
+  int32_t reserved;
+  double tau;
+  double magic;          /* TRT Lambda, e.g. 3/16                               */
+  double omega_bulk;     /* cumulant trace rate, e.g. 1                         */
+  double force[3];
+} lbm_collision;
+
+/* Boundary classes for labels 2..9.  UBB: moving wall u (bounce-back plus
+ * 6 w_i rho_w c_i.u, rho_w = 1); PRESSURE: anti-bounce-back to density rho
+ * (-f + 2 w_i rho, the O(u^2) term dropped); NOSLIP: plain bounce-back. */
+typedef struct {
+  int32_t type;          /* LBM_BC_*                                           */
+  int32_t reserved;
+  double u[3];
+  double rho;
+} lbm_bclass;
+typedef struct {
+  int32_t n_classes;     /* 0..8                                               */
+  int32_t reserved;
+  lbm_bclass cls[8];
+} lbm_bspec;
+
+/* Initialise every fluid cell to the equilibrium of (rho0, u0) and set
+ * state->t = 0.  u0: host double[3].  Padding slots are zeroed (deviation)
+ * or set to the weights.  Errors: LBM_EINVAL, LBM_EDEVICE. */
+lbm_status lbm_init_equilibrium(lbm_state* state, double rho0, const double* u0, void* stream);
+
+/* Advance n_steps >= 0 AA steps (Section "In-place Streaming: AA Pattern").
+ * For each step: apply the boundary links (if n_links > 0), then run the
+ * odd kernel when t is even (gather through the index-list, collide, write
+ * each result back to the slot its opposite population came from) or the
+ * even kernel when t is odd (collide reading opposite slots, write natural
+ * slots); t += 1.  bspec may be NULL when n_links == 0.
+ * Errors: LBM_EINVAL (tau <= 1/2, cumulant with q != 27, storage/dev_exp),
+ *         LBM_ESTATE, LBM_EDEVICE. */
+lbm_status lbm_step(lbm_state* state, int32_t n_steps, const lbm_collision* coll,
+                    const lbm_bspec* bspec, void* stream);
+
+/* Density and velocity of every fluid cell at the current t (either
+ * parity), from the post-collision populations: rho = sum f*,
+ * u = (sum c f* - F/2) / rho.
+ *  rho  device, stride elements; u device, 3*stride elements (u_x block,
+ *       u_y block, u_z block); element type double if out_f64 else float. */
+lbm_status lbm_moments(const lbm_state* state, const lbm_collision* coll, int32_t out_f64,
+                       void* rho, void* u, void* stream);
+
+/* FP64 global reductions over fluid cells (either parity):
+ * mass = sum rho, mom = sum rho*u.  Deterministic: fixed per-tile tree then
+ * a fixed-order second pass.  SYNC.  Returns LBM_EUNSTABLE (with the
+ * result filled and finite = 0) if any value was NaN or Inf. */
+typedef struct {
+  double mass;
+  double mom[3];
+  int64_t n_fluid;
+  int32_t finite;
+  int32_t reserved;
+} lbm_reduction;
+
+uint64_t lbm_reduce_workspace_bytes(const lbm_layout* layout);
+lbm_status lbm_reduce(const lbm_state* state, const lbm_collision* coll, void* workspace,
+                      lbm_reduction* host_out, void* stream);
+
+/* ------------------------------------------------------------------ */
+/* Batching: one launch per step advances many independent states in     */
+/* lockstep parity.  Each state keeps its own buffers; kernels never mix */
+/* two states in one workgroup, so every result is bitwise identical to  */
+/* running the state alone with the same launch configuration.           */
+/* ------------------------------------------------------------------ */
+
+/* states[n], colls[n], bspecs[n] (bspecs may be NULL): every state must
+ * have the same q, storage and parity (t & 1).  Errors: LBM_ESTATE when
+ * they differ, otherwise as lbm_step. */
+lbm_status lbm_step_batch(lbm_state* const* states, const lbm_collision* const* colls,
+                          const lbm_bspec* const* bspecs, int32_t n_states, int32_t n_steps,
+                          void* stream);
+
+/* Per-state reductions of lbm_reduce for n states at once, bitwise equal
+ * to calling lbm_reduce on each.  workspace >= sum of
+ * lbm_reduce_workspace_bytes over the states.  host_out[n].  SYNC. */
+lbm_status lbm_reduce_batch(const lbm_state* const* states, const lbm_collision* const* colls,
+                            int32_t n_states, void* workspace, lbm_reduction* host_out,
+                            void* stream);
+
+/* ------------------------------------------------------------------ */
+/* Dense direct-addressing comparator (Section "Single Node Results":    */
+/* the dense kernel traverses every cell, fluid or not, without a fluid  */
+/* branch).  AA pattern over all N = nx*ny*nz cells, PDF element i*N +   */
+/* lin; bounce-back from a per-cell uint32 mask (bit i set: the upstream */
+/* cell x - c_i is not fluid).  Labels >= 2 act as no-slip here.         */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+  int32_t nx, ny, nz;
+  uint32_t periodic;
+  int32_t q;
+  int32_t storage;
+  int32_t dev_exp;
+  int32_t reserved;
+  void* pdf;             /* device, q*N elements                               */
+  const uint32_t* mask;  /* device, N                                          */
+  int64_t t;
+} lbm_dense_state;
+
+/* labels device uint8[N]; mask device uint32[N]. */
+lbm_status lbm_dense_build_mask(const uint8_t* labels, int32_t nx, int32_t ny, int32_t nz,
+                                uint32_t periodic, int32_t q, uint32_t* mask, void* stream);
+lbm_status lbm_dense_init_equilibrium(lbm_dense_state* state, double rho0, const double* u0,
+                                      void* stream);
+lbm_status lbm_dense_step(lbm_dense_state* state, int32_t n_steps, const lbm_collision* coll,
+                          void* stream);
+
+/* ------------------------------------------------------------------ */
+/* Launch configuration and measurement helpers.                        */
+/* ------------------------------------------------------------------ */
+
+enum { LBM_KERNEL_ODD = 0, LBM_KERNEL_EVEN = 1, LBM_KERNEL_DENSE = 2 };
+typedef struct {
+  int32_t block;      /* threads per workgroup: 64, 128 or 256                 */
+  int32_t xcd_remap;  /* 1: contiguous tile ranges per XCD (8 XCDs)            */
+  int32_t reserved[2];
+} lbm_launch;
+
+/* Set / get the launch configuration used for (kernel, q, storage) from
+ * now on, process-wide (e.g. from an autotuner cache).  Changing it does
+ * not change results except through workgroup-to-tile assignment, which
+ * the arithmetic does not depend on. */
+lbm_status lbm_set_launch(int32_t kernel, int32_t q, int32_t storage, const lbm_launch* cfg);
+lbm_status lbm_get_launch(int32_t kernel, int32_t q, int32_t storage, lbm_launch* cfg);
+
+/* Streaming copy dst[0..bytes) = src[0..bytes) with 16-byte vector loads;
+ * device pointers, 16-byte aligned, bytes a multiple of 16.  Reference for
+ * the achievable HBM bandwidth and for hardware byte counters. */
+lbm_status lbm_copy(void* dst, const void* src, uint64_t bytes, void* stream);
+
+const char* lbm_last_error(void);
+int32_t lbm_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -93,6 +93,7 @@ def _load():
         P = ctypes.POINTER(Params)
         vp = ctypes.c_void_p
         i32, i64, u32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+        lib.orc_num_threads.restype = ctypes.c_int
         lib.orc_stencil_tables.argtypes = [i32, vp, vp, vp]
         lib.orc_collide_cells.argtypes = [P, i64, vp, vp]
         lib.orc_dense_step.argtypes = [P, vp, i32, i32, i32, u32, vp, vp]
@@ -119,6 +120,11 @@ def _ptr(a: np.ndarray):
 def _check(rc, what):
     if rc != 0:
         raise RuntimeError(f"oracle {what} failed with code {rc}")
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(_load().orc_num_threads())
 
 
 def stencil(q):

@@ -1,0 +1,533 @@
+// C-ABI of liblbm.so: argument validation, launch planning and kernel
+// dispatch.  No entry point allocates device memory; all buffers and the
+// stream belong to the caller.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+
+#include "../../include/lbm.h"
+#include "internal.hpp"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+lbm_status fail(lbm_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+lbm_status hip_fail(hipError_t e, const char* where) {
+  return fail(LBM_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, where)              \
+  do {                                    \
+    hipError_t e_ = (expr);               \
+    if (e_ != hipSuccess) return hip_fail(e_, where); \
+  } while (0)
+
+// ------------------------------------------------------- launch table
+std::mutex g_launch_mu;
+lbm_launch g_launch[3][2][5];  // kernel x (q19, q27) x storage
+bool g_launch_init = false;
+
+void launch_defaults() {
+  if (g_launch_init) return;
+  for (auto& a : g_launch)
+    for (auto& b : a)
+      for (auto& c : b) {
+        c.block = 256;
+        c.xcd_remap = 1;
+        c.reserved[0] = c.reserved[1] = 0;
+      }
+  g_launch_init = true;
+}
+
+lbm_launch get_cfg(int kernel, int q, int storage) {
+  std::lock_guard<std::mutex> lk(g_launch_mu);
+  launch_defaults();
+  return g_launch[kernel][q == 27 ? 1 : 0][storage];
+}
+
+// ------------------------------------------------------- validation
+bool storage_ok(int s) { return s >= LBM_STORE_F64 && s <= LBM_STORE_F32DEV; }
+bool is16(int s) { return s == LBM_STORE_F16DEV || s == LBM_STORE_BF16DEV; }
+
+lbm_status check_layout(const lbm_layout& L) {
+  if (L.q != 19 && L.q != 27) return fail(LBM_EINVAL, "layout.q must be 19 or 27 (got %d)", L.q);
+  if (L.n_fluid < 0 || L.stride < L.n_fluid || L.n_links < 0)
+    return fail(LBM_EINVAL, "inconsistent layout sizes (n_fluid %lld, stride %lld)",
+                (long long)L.n_fluid, (long long)L.stride);
+  if ((int64_t)L.q * L.stride >= (int64_t)1 << 31)
+    return fail(LBM_ERANGE, "q*stride = %lld does not fit int32 positions",
+                (long long)L.q * L.stride);
+  return LBM_OK;
+}
+
+lbm_status check_state(const lbm_state* s) {
+  if (!s) return fail(LBM_EINVAL, "state is NULL");
+  lbm_status rc = check_layout(s->layout);
+  if (rc) return rc;
+  if (!storage_ok(s->storage)) return fail(LBM_EINVAL, "unknown storage %d", s->storage);
+  if (is16(s->storage) && (s->dev_exp < 0 || s->dev_exp > 24))
+    return fail(LBM_EINVAL, "dev_exp must be in [0, 24] (got %d)", s->dev_exp);
+  if (s->layout.n_fluid > 0 && (!s->pdf || !s->index))
+    return fail(LBM_EINVAL, "state pdf/index pointer is NULL");
+  if (s->layout.n_links > 0 && !s->links)
+    return fail(LBM_EINVAL, "state has %lld links but links is NULL", (long long)s->layout.n_links);
+  if (s->t < 0) return fail(LBM_EINVAL, "state.t is negative");
+  return LBM_OK;
+}
+
+lbm_status check_coll(const lbm_collision* c, int q) {
+  if (!c) return fail(LBM_EINVAL, "collision is NULL");
+  if (c->kind < LBM_COLL_NONE || c->kind > LBM_COLL_CUMULANT)
+    return fail(LBM_EINVAL, "unknown collision kind %d", c->kind);
+  if (c->kind != LBM_COLL_NONE && !(c->tau > 0.5))
+    return fail(LBM_EINVAL, "tau must be > 1/2 (got %g)", c->tau);
+  if (c->kind == LBM_COLL_TRT && !(c->magic > 0.0))
+    return fail(LBM_EINVAL, "TRT magic parameter must be > 0 (got %g)", c->magic);
+  if (c->kind == LBM_COLL_CUMULANT && q != 27)
+    return fail(LBM_EINVAL, "the cumulant operator needs D3Q27");
+  if (c->kind == LBM_COLL_CUMULANT && !(c->omega_bulk > 0.0 && c->omega_bulk < 2.0))
+    return fail(LBM_EINVAL, "omega_bulk must be in (0, 2) (got %g)", c->omega_bulk);
+  for (int a = 0; a < 3; ++a)
+    if (!isfinite(c->force[a])) return fail(LBM_EINVAL, "force must be finite");
+  return LBM_OK;
+}
+
+void coll_rates(const lbm_collision* c, double& om1, double& om2) {
+  om1 = om2 = 0.0;
+  if (c->kind == LBM_COLL_SRT) {
+    om1 = om2 = 1.0 / c->tau;
+  } else if (c->kind == LBM_COLL_TRT) {
+    om1 = 1.0 / c->tau;
+    om2 = 1.0 / (0.5 + c->magic / (c->tau - 0.5));
+  } else if (c->kind == LBM_COLL_CUMULANT) {
+    om1 = 1.0 / c->tau;
+    om2 = c->omega_bulk;
+  }
+}
+
+Seg make_seg(const lbm_state* s, const lbm_collision* c) {
+  Seg g;
+  memset(&g, 0, sizeof(g));
+  g.pdf = s->pdf;
+  g.idx = s->index;
+  g.S = (uint32_t)s->layout.stride;
+  g.nf = (uint32_t)s->layout.n_fluid;
+  if (c) {
+    coll_rates(c, g.om1, g.om2);
+    for (int a = 0; a < 3; ++a) g.F[a] = c->force[a];
+  }
+  const int e = is16(s->storage) ? s->dev_exp : 0;
+  g.scale = ldexpf(1.0f, e);
+  g.inv_scale = ldexpf(1.0f, -e);
+  return g;
+}
+
+lbm_status link_update(const lbm_state* s, const lbm_bspec* bs, hipStream_t st) {
+  if (s->layout.n_links == 0) return LBM_OK;
+  LinkArgs la;
+  memset(&la, 0, sizeof(la));
+  la.pdf = s->pdf;
+  la.links = s->links;
+  la.n_links = (uint32_t)s->layout.n_links;
+  la.q = s->layout.q;
+  la.n_classes = bs ? bs->n_classes : 0;
+  if (la.n_classes < 0 || la.n_classes > 8)
+    return fail(LBM_EINVAL, "bspec.n_classes must be in [0, 8]");
+  for (int c = 0; c < la.n_classes; ++c) {
+    const int ty = bs->cls[c].type;
+    if (ty < LBM_BC_NOSLIP || ty > LBM_BC_PRESSURE)
+      return fail(LBM_EINVAL, "unknown boundary type %d in class %d", ty, c);
+    la.type[c] = ty;
+    for (int a = 0; a < 3; ++a) la.u[c][a] = bs->cls[c].u[a];
+    la.rho[c] = bs->cls[c].rho;
+  }
+  const int e = is16(s->storage) ? s->dev_exp : 0;
+  la.scale = ldexpf(1.0f, e);
+  la.inv_scale = ldexpf(1.0f, -e);
+  HIP_TRY(launch_links(s->storage, la, st), "link update");
+  return LBM_OK;
+}
+
+hipError_t launch_aa(int q, int coll, int storage, bool odd, const StepArgs& a, int block,
+                     hipStream_t st) {
+  if (q == 19) return launch_aa_q19(coll, storage, odd, a, block, st);
+  return launch_aa_q27(coll, storage, odd, a, block, st);
+}
+
+uint64_t align256(uint64_t v) { return (v + 255) & ~(uint64_t)255; }
+
+uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+}  // namespace
+
+extern "C" {
+
+int32_t lbm_abi_version(void) { return 1; }
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+lbm_status lbm_set_launch(int32_t kernel, int32_t q, int32_t storage, const lbm_launch* cfg) {
+  if (kernel < 0 || kernel > 2 || (q != 19 && q != 27) || !storage_ok(storage) || !cfg)
+    return fail(LBM_EINVAL, "lbm_set_launch: bad kernel/q/storage");
+  if (cfg->block != 64 && cfg->block != 128 && cfg->block != 256)
+    return fail(LBM_EINVAL, "block must be 64, 128 or 256 (got %d)", cfg->block);
+  std::lock_guard<std::mutex> lk(g_launch_mu);
+  launch_defaults();
+  g_launch[kernel][q == 27 ? 1 : 0][storage] = *cfg;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_launch(int32_t kernel, int32_t q, int32_t storage, lbm_launch* cfg) {
+  if (kernel < 0 || kernel > 2 || (q != 19 && q != 27) || !storage_ok(storage) || !cfg)
+    return fail(LBM_EINVAL, "lbm_get_launch: bad kernel/q/storage");
+  *cfg = get_cfg(kernel, q, storage);
+  return LBM_OK;
+}
+
+// ------------------------------------------------------------ builder
+static bool build_dims_ok(int32_t nx, int32_t ny, int32_t nz) {
+  return nx >= 1 && ny >= 1 && nz >= 1 && nx <= 1024 && ny <= 1024 && nz <= 1024;
+}
+
+static void build_plan(int32_t nx, int32_t ny, int32_t nz, int32_t order, uint32_t& bits,
+                       uint64_t& n_codes, uint32_t& n_chunks) {
+  const int32_t m = nx > ny ? (nx > nz ? nx : nz) : (ny > nz ? ny : nz);
+  bits = 0;
+  while ((1 << bits) < m) ++bits;
+  n_codes = order == LBM_ORDER_MORTON ? (uint64_t)1 << (3 * bits) : (uint64_t)nx * ny * nz;
+  n_chunks = ceil_div(n_codes, kChunk);
+}
+
+uint64_t lbm_build_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t order) {
+  if (!build_dims_ok(nx, ny, nz) || (order != 0 && order != 1)) return 0;
+  uint32_t bits, n_chunks;
+  uint64_t n_codes;
+  build_plan(nx, ny, nz, order, bits, n_codes, n_chunks);
+  return align256((uint64_t)8 * (n_chunks + 1)) + (uint64_t)4 * nx * ny * nz;
+}
+
+lbm_status lbm_build_sparse(const uint8_t* labels, int32_t nx, int32_t ny, int32_t nz,
+                            uint32_t periodic, int32_t q, int32_t order, int32_t align,
+                            void* workspace, lbm_layout* layout, int32_t* cells, int32_t* index,
+                            int32_t* links, void* stream) {
+  if (!labels || !workspace || !layout) return fail(LBM_EINVAL, "labels/workspace/layout is NULL");
+  if (!build_dims_ok(nx, ny, nz)) return fail(LBM_EINVAL, "box sizes must be in [1, 1024]");
+  if (q != 19 && q != 27) return fail(LBM_EINVAL, "q must be 19 or 27");
+  if (order != LBM_ORDER_MORTON && order != LBM_ORDER_LEX) return fail(LBM_EINVAL, "bad order");
+  if (align < 1) return fail(LBM_EINVAL, "align must be >= 1");
+  if (periodic > 7u) return fail(LBM_EINVAL, "periodic must be a 3-bit mask");
+  hipStream_t st = (hipStream_t)stream;
+  BuildArgs b;
+  b.labels = labels;
+  b.nx = nx;
+  b.ny = ny;
+  b.nz = nz;
+  b.periodic = periodic;
+  b.q = q;
+  b.order = order;
+  build_plan(nx, ny, nz, order, b.bits, b.n_codes, b.n_chunks);
+  uint32_t* counts = (uint32_t*)workspace;
+  int32_t* inv = (int32_t*)((char*)workspace + align256((uint64_t)8 * (b.n_chunks + 1)));
+  HIP_TRY(launch_build_count(b, counts, st), "build count");
+  HIP_TRY(launch_build_scan(b.n_chunks, counts, st), "build scan");
+  if (!cells) {
+    if (index || links) return fail(LBM_EINVAL, "plan call: index and links must be NULL");
+    uint32_t tot[2];
+    HIP_TRY(hipMemcpyAsync(&tot[0], counts + b.n_chunks, 4, hipMemcpyDeviceToHost, st), "plan copy");
+    HIP_TRY(hipMemcpyAsync(&tot[1], counts + 2 * b.n_chunks + 1, 4, hipMemcpyDeviceToHost, st),
+            "plan copy");
+    HIP_TRY(hipStreamSynchronize(st), "plan sync");
+    lbm_layout L;
+    memset(&L, 0, sizeof(L));
+    L.nx = nx;
+    L.ny = ny;
+    L.nz = nz;
+    L.periodic = periodic;
+    L.q = q;
+    L.order = order;
+    L.align = align;
+    L.n_fluid = tot[0];
+    L.stride = ((L.n_fluid + align - 1) / align) * align;
+    L.n_links = tot[1];
+    *layout = L;
+    return check_layout(L);
+  }
+  const lbm_layout& L = *layout;
+  if (L.nx != nx || L.ny != ny || L.nz != nz || L.q != q || L.order != order ||
+      L.periodic != periodic || L.align != align)
+    return fail(LBM_ESTATE, "fill call: layout does not match the arguments");
+  lbm_status rc = check_layout(L);
+  if (rc) return rc;
+  if (!index) return fail(LBM_EINVAL, "fill call: index is NULL");
+  if (L.n_links > 0 && !links) return fail(LBM_EINVAL, "fill call: links is NULL");
+  HIP_TRY(launch_build_emit(b, counts, (uint32_t)L.stride, (uint32_t)L.n_fluid,
+                            (uint32_t)L.n_links, cells, inv, links, st),
+          "build emit");
+  HIP_TRY(launch_build_index(b, cells, inv, (uint32_t)L.stride, (uint32_t)L.n_fluid, index, st),
+          "build index");
+  return LBM_OK;
+}
+
+// ---------------------------------------------------------- stepping
+lbm_status lbm_init_equilibrium(lbm_state* s, double rho0, const double* u0, void* stream) {
+  lbm_status rc = check_state(s);
+  if (rc) return rc;
+  if (!u0 || !(rho0 > 0.0)) return fail(LBM_EINVAL, "rho0 must be > 0 and u0 non-NULL");
+  const int e = is16(s->storage) ? s->dev_exp : 0;
+  if (s->layout.stride > 0)
+    HIP_TRY(launch_init(s->layout.q, s->storage, s->pdf, (uint32_t)s->layout.stride,
+                        (uint32_t)s->layout.n_fluid, rho0, u0, ldexpf(1.0f, e),
+                        (hipStream_t)stream),
+            "init");
+  s->t = 0;
+  return LBM_OK;
+}
+
+static lbm_status step_group(lbm_state* const* states, const lbm_collision* const* colls,
+                             const lbm_bspec* const* bspecs, int32_t n, int32_t n_steps,
+                             hipStream_t st) {
+  const int q = states[0]->layout.q, storage = states[0]->storage;
+  const int kind = colls[0]->kind;
+  for (int32_t step = 0; step < n_steps; ++step) {
+    const bool odd = (states[0]->t & 1) == 0;
+    const lbm_launch cfg = get_cfg(odd ? LBM_KERNEL_ODD : LBM_KERNEL_EVEN, q, storage);
+    for (int32_t j = 0; j < n; ++j) {
+      lbm_status rc = link_update(states[j], bspecs ? bspecs[j] : nullptr, st);
+      if (rc) return rc;
+    }
+    for (int32_t j0 = 0; j0 < n; j0 += kMaxSeg) {
+      StepArgs a;
+      memset(&a, 0, sizeof(a));
+      a.xcd_remap = cfg.xcd_remap;
+      uint32_t tiles = 0;
+      int ns = 0;
+      for (int32_t j = j0; j < n && j < j0 + kMaxSeg; ++j) {
+        if (states[j]->layout.n_fluid == 0) continue;
+        Seg g = make_seg(states[j], colls[j]);
+        g.tile0 = tiles;
+        tiles += ceil_div(g.nf, (uint64_t)cfg.block);
+        a.seg[ns++] = g;
+      }
+      a.nseg = ns;
+      a.ntiles = tiles;
+      if (ns > 0) HIP_TRY(launch_aa(q, kind, storage, odd, a, cfg.block, st), "AA step");
+    }
+    for (int32_t j = 0; j < n; ++j) states[j]->t += 1;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_state* s, int32_t n_steps, const lbm_collision* c, const lbm_bspec* bs,
+                    void* stream) {
+  lbm_status rc = check_state(s);
+  if (rc) return rc;
+  rc = check_coll(c, s->layout.q);
+  if (rc) return rc;
+  if (n_steps < 0) return fail(LBM_EINVAL, "n_steps must be >= 0");
+  lbm_state* arr[1] = {s};
+  const lbm_collision* carr[1] = {c};
+  const lbm_bspec* barr[1] = {bs};
+  return step_group(arr, carr, barr, 1, n_steps, (hipStream_t)stream);
+}
+
+lbm_status lbm_step_batch(lbm_state* const* states, const lbm_collision* const* colls,
+                          const lbm_bspec* const* bspecs, int32_t n, int32_t n_steps,
+                          void* stream) {
+  if (!states || !colls || n < 1) return fail(LBM_EINVAL, "lbm_step_batch: empty batch");
+  if (n_steps < 0) return fail(LBM_EINVAL, "n_steps must be >= 0");
+  for (int32_t j = 0; j < n; ++j) {
+    lbm_status rc = check_state(states[j]);
+    if (rc) return rc;
+    rc = check_coll(colls[j], states[j]->layout.q);
+    if (rc) return rc;
+    if (states[j]->layout.q != states[0]->layout.q || states[j]->storage != states[0]->storage ||
+        ((states[j]->t ^ states[0]->t) & 1) || colls[j]->kind != colls[0]->kind)
+      return fail(LBM_ESTATE, "batch member %d differs in q, storage, parity or collision kind", j);
+  }
+  return step_group(states, colls, bspecs, n, n_steps, (hipStream_t)stream);
+}
+
+lbm_status lbm_moments(const lbm_state* s, const lbm_collision* c, int32_t out_f64, void* rho,
+                       void* u, void* stream) {
+  lbm_status rc = check_state(s);
+  if (rc) return rc;
+  rc = check_coll(c, s->layout.q);
+  if (rc) return rc;
+  if (s->layout.n_fluid > 0 && (!rho || !u)) return fail(LBM_EINVAL, "rho/u is NULL");
+  Seg g = make_seg(s, c);
+  HIP_TRY(launch_moments(s->layout.q, s->storage, g, (s->t & 1) != 0, out_f64 != 0, rho, u,
+                         (hipStream_t)stream),
+          "moments");
+  return LBM_OK;
+}
+
+uint64_t lbm_reduce_workspace_bytes(const lbm_layout* L) {
+  if (!L || L->n_fluid < 0) return 0;
+  return align256((uint64_t)ceil_div((uint64_t)L->n_fluid, kRedBlock) * 5 * sizeof(double)) + 256;
+}
+
+lbm_status lbm_reduce_batch(const lbm_state* const* states, const lbm_collision* const* colls,
+                            int32_t n, void* workspace, lbm_reduction* out, void* stream) {
+  if (!states || !colls || n < 1 || !out) return fail(LBM_EINVAL, "lbm_reduce_batch: bad arguments");
+  if (!workspace) return fail(LBM_EINVAL, "workspace is NULL");
+  for (int32_t j = 0; j < n; ++j) {
+    lbm_status rc = check_state(states[j]);
+    if (rc) return rc;
+    rc = check_coll(colls[j], states[j]->layout.q);
+    if (rc) return rc;
+    if (states[j]->layout.q != states[0]->layout.q || states[j]->storage != states[0]->storage ||
+        ((states[j]->t ^ states[0]->t) & 1))
+      return fail(LBM_ESTATE, "batch member %d differs in q, storage or parity", j);
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int q = states[0]->layout.q, storage = states[0]->storage;
+  const bool odd_t = (states[0]->t & 1) != 0;
+  char* ws = (char*)workspace;
+  bool finite_all = true;
+  for (int32_t j0 = 0; j0 < n; j0 += kMaxSeg) {
+    StepArgs a;
+    memset(&a, 0, sizeof(a));
+    uint32_t tiles = 0;
+    int ns = 0;
+    uint64_t bytes = 0;
+    for (int32_t j = j0; j < n && j < j0 + kMaxSeg; ++j) {
+      Seg g = make_seg(states[j], colls[j]);
+      g.tile0 = tiles;
+      tiles += ceil_div(g.nf, kRedBlock);
+      a.seg[ns++] = g;
+      bytes += lbm_reduce_workspace_bytes(&states[j]->layout);
+    }
+    a.nseg = ns;
+    a.ntiles = tiles;
+    double* partials = (double*)ws;
+    double* dout = (double*)(ws + align256((uint64_t)tiles * 5 * sizeof(double)));
+    HIP_TRY(launch_reduce(q, storage, a, odd_t, partials, dout, st), "reduce");
+    double host[kMaxSeg * 8];
+    HIP_TRY(hipMemcpyAsync(host, dout, sizeof(double) * 8 * ns, hipMemcpyDeviceToHost, st),
+            "reduce copy");
+    HIP_TRY(hipStreamSynchronize(st), "reduce sync");
+    for (int j = 0; j < ns; ++j) {
+      lbm_reduction& r = out[j0 + j];
+      r.mass = host[j * 8 + 0];
+      r.mom[0] = host[j * 8 + 2];
+      r.mom[1] = host[j * 8 + 3];
+      r.mom[2] = host[j * 8 + 4];
+      r.n_fluid = (int64_t)host[j * 8 + 6];
+      r.finite = (host[j * 8 + 5] == 0.0 && isfinite(r.mass) && isfinite(r.mom[0]) &&
+                  isfinite(r.mom[1]) && isfinite(r.mom[2]))
+                     ? 1
+                     : 0;
+      r.reserved = 0;
+      finite_all = finite_all && r.finite;
+    }
+    ws += bytes;
+  }
+  if (!finite_all) return fail(LBM_EUNSTABLE, "non-finite values in the reduction");
+  return LBM_OK;
+}
+
+lbm_status lbm_reduce(const lbm_state* s, const lbm_collision* c, void* workspace,
+                      lbm_reduction* out, void* stream) {
+  const lbm_state* arr[1] = {s};
+  const lbm_collision* carr[1] = {c};
+  return lbm_reduce_batch(arr, carr, 1, workspace, out, stream);
+}
+
+// ------------------------------------------------------------- dense
+lbm_status lbm_dense_build_mask(const uint8_t* labels, int32_t nx, int32_t ny, int32_t nz,
+                                uint32_t periodic, int32_t q, uint32_t* mask, void* stream) {
+  if (!labels || !mask) return fail(LBM_EINVAL, "labels/mask is NULL");
+  if (!build_dims_ok(nx, ny, nz)) return fail(LBM_EINVAL, "box sizes must be in [1, 1024]");
+  if (q != 19 && q != 27) return fail(LBM_EINVAL, "q must be 19 or 27");
+  if (periodic > 7u) return fail(LBM_EINVAL, "periodic must be a 3-bit mask");
+  HIP_TRY(launch_dense_mask(labels, nx, ny, nz, periodic, q, mask, (hipStream_t)stream),
+          "dense mask");
+  return LBM_OK;
+}
+
+static lbm_status check_dense(const lbm_dense_state* s) {
+  if (!s) return fail(LBM_EINVAL, "dense state is NULL");
+  if (s->q != 19 && s->q != 27) return fail(LBM_EINVAL, "q must be 19 or 27");
+  if (!build_dims_ok(s->nx, s->ny, s->nz)) return fail(LBM_EINVAL, "box sizes must be in [1, 1024]");
+  if (!storage_ok(s->storage)) return fail(LBM_EINVAL, "unknown storage");
+  if (is16(s->storage) && (s->dev_exp < 0 || s->dev_exp > 24))
+    return fail(LBM_EINVAL, "dev_exp must be in [0, 24]");
+  const int64_t N = (int64_t)s->nx * s->ny * s->nz;
+  if ((int64_t)s->q * N >= (int64_t)1 << 31) return fail(LBM_ERANGE, "q*N does not fit int32");
+  if (!s->pdf || !s->mask) return fail(LBM_EINVAL, "pdf/mask is NULL");
+  return LBM_OK;
+}
+
+lbm_status lbm_dense_init_equilibrium(lbm_dense_state* s, double rho0, const double* u0,
+                                      void* stream) {
+  lbm_status rc = check_dense(s);
+  if (rc) return rc;
+  if (!u0 || !(rho0 > 0.0)) return fail(LBM_EINVAL, "rho0 must be > 0 and u0 non-NULL");
+  const uint32_t N = (uint32_t)((int64_t)s->nx * s->ny * s->nz);
+  const int e = is16(s->storage) ? s->dev_exp : 0;
+  HIP_TRY(launch_init(s->q, s->storage, s->pdf, N, N, rho0, u0, ldexpf(1.0f, e),
+                      (hipStream_t)stream),
+          "dense init");
+  s->t = 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_dense_step(lbm_dense_state* s, int32_t n_steps, const lbm_collision* c,
+                          void* stream) {
+  lbm_status rc = check_dense(s);
+  if (rc) return rc;
+  rc = check_coll(c, s->q);
+  if (rc) return rc;
+  if (n_steps < 0) return fail(LBM_EINVAL, "n_steps must be >= 0");
+  const lbm_launch cfg = get_cfg(LBM_KERNEL_DENSE, s->q, s->storage);
+  DenseArgs a;
+  memset(&a, 0, sizeof(a));
+  a.pdf = s->pdf;
+  a.mask = s->mask;
+  a.nx = s->nx;
+  a.ny = s->ny;
+  a.nz = s->nz;
+  a.periodic = s->periodic;
+  a.N = (uint32_t)((int64_t)s->nx * s->ny * s->nz);
+  a.xcd_remap = cfg.xcd_remap;
+  a.ntiles = ceil_div(a.N, (uint64_t)cfg.block);
+  coll_rates(c, a.om1, a.om2);
+  for (int k = 0; k < 3; ++k) a.F[k] = c->force[k];
+  const int e = is16(s->storage) ? s->dev_exp : 0;
+  a.scale = ldexpf(1.0f, e);
+  a.inv_scale = ldexpf(1.0f, -e);
+  for (int32_t step = 0; step < n_steps; ++step) {
+    const bool odd = (s->t & 1) == 0;
+    HIP_TRY(launch_dense_step(s->q, c->kind, s->storage, odd, a, cfg.block, (hipStream_t)stream),
+            "dense step");
+    s->t += 1;
+  }
+  return LBM_OK;
+}
+
+// --------------------------------------------------------------- copy
+lbm_status lbm_copy(void* dst, const void* src, uint64_t bytes, void* stream) {
+  if (!dst || !src) return fail(LBM_EINVAL, "copy: NULL pointer");
+  if ((bytes & 15) || ((uintptr_t)dst & 15) || ((uintptr_t)src & 15))
+    return fail(LBM_EINVAL, "copy: pointers and size must be 16-byte aligned");
+  HIP_TRY(launch_copy(dst, src, bytes, (hipStream_t)stream), "copy");
+  return LBM_OK;
+}
+
+}  // extern "C"

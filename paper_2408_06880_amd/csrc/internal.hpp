@@ -1,0 +1,87 @@
+// Host-side launch entry points shared between the translation units of
+// liblbm.so (not part of the public C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lattice.hpp"
+
+namespace lbm {
+
+// AA step kernels (step_q19.hip, step_q27.hip)
+hipError_t launch_aa_q19(int coll, int storage, bool odd, const StepArgs& a, int block,
+                         hipStream_t st);
+hipError_t launch_aa_q27(int coll, int storage, bool odd, const StepArgs& a, int block,
+                         hipStream_t st);
+
+// Boundary-class coefficients of one solve, precomputed on the host:
+// for class c, type[c] in {0 noslip, 1 UBB, 2 pressure}; u[c][3]; rho[c].
+struct LinkArgs {
+  void* pdf;
+  const int32_t* links;
+  uint32_t n_links;
+  int32_t q;
+  int32_t n_classes;
+  int32_t type[8];
+  double u[8][3];
+  double rho[8];
+  float scale, inv_scale;
+};
+
+// aux.hip
+hipError_t launch_init(int q, int storage, void* pdf, uint32_t S, uint32_t nf, double rho0,
+                       const double u0[3], float scale, hipStream_t st);
+hipError_t launch_links(int storage, const LinkArgs& a, hipStream_t st);
+hipError_t launch_moments(int q, int storage, const Seg& g, bool odd_t, bool out_f64, void* rho,
+                          void* u, hipStream_t st);
+// Reductions: first pass writes 5 doubles per tile of kRedBlock cells into
+// partials (tiles of all segments in launch order); the second pass writes
+// 8 doubles per segment into out.
+constexpr int kRedBlock = 256;
+hipError_t launch_reduce(int q, int storage, const StepArgs& a, bool odd_t, double* partials,
+                         double* out, hipStream_t st);
+hipError_t launch_copy(void* dst, const void* src, uint64_t bytes, hipStream_t st);
+
+// builder.hip
+struct BuildArgs {
+  const uint8_t* labels;
+  int32_t nx, ny, nz;
+  uint32_t periodic;
+  int32_t q, order;
+  uint32_t bits;        // Morton bits per axis (order == Morton)
+  uint64_t n_codes;     // codes to scan (8^bits for Morton, nx*ny*nz for lex)
+  uint32_t n_chunks;    // ceil(n_codes / kChunk)
+};
+constexpr int kBuildBlock = 256;
+constexpr int kCodesPerThread = 16;
+constexpr uint32_t kChunk = kBuildBlock * kCodesPerThread;
+// counts: uint32[2*(n_chunks+1)] (fluid cells, links per chunk -> exclusive
+// offsets after the scan, totals at [n_chunks]).
+hipError_t launch_build_count(const BuildArgs& b, uint32_t* counts, hipStream_t st);
+hipError_t launch_build_scan(uint32_t n_chunks, uint32_t* counts, hipStream_t st);
+hipError_t launch_build_emit(const BuildArgs& b, const uint32_t* counts, uint32_t S,
+                             uint32_t n_fluid, uint32_t n_links, int32_t* cells, int32_t* inv,
+                             int32_t* links, hipStream_t st);
+hipError_t launch_build_index(const BuildArgs& b, const int32_t* cells, const int32_t* inv,
+                              uint32_t S, uint32_t n_fluid, int32_t* index, hipStream_t st);
+
+// dense.hip
+struct DenseArgs {
+  void* pdf;
+  const uint32_t* mask;
+  int32_t nx, ny, nz;
+  uint32_t periodic;
+  uint32_t N;
+  int32_t xcd_remap;
+  uint32_t ntiles;
+  int32_t pad;
+  double om1, om2, F[3];
+  float scale, inv_scale;
+};
+hipError_t launch_dense_mask(const uint8_t* labels, int nx, int ny, int nz, uint32_t periodic,
+                             int q, uint32_t* mask, hipStream_t st);
+hipError_t launch_dense_step(int q, int coll, int storage, bool odd, const DenseArgs& a,
+                             int block, hipStream_t st);
+
+}  // namespace lbm

@@ -1,0 +1,152 @@
+// Velocity sets, storage codecs and launch-argument types of the sparse AA
+// lattice Boltzmann kernels (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// D3Q19 / D3Q27 velocity sets: rest, then opposite pairs (axes, edges,
+// corners).  Weights 1/3, 1/18, 1/36 (D3Q19) and 8/27, 2/27, 1/54, 1/216
+// (D3Q27); speed of sound c_s^2 = 1/3 (Section "Lattice Boltzmann Method").
+// ---------------------------------------------------------------------------
+template <int Q>
+struct Lattice;
+
+template <>
+struct Lattice<19> {
+  static constexpr int cx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+  static constexpr int cy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+  static constexpr int cz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+  static constexpr double w(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
+};
+
+template <>
+struct Lattice<27> {
+  static constexpr int cx[27] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1,
+                                 -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, -1, 1};
+  static constexpr int cy[27] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0,
+                                 0, 1, -1, 1, -1, 1, -1, 1, -1, -1, 1, 1, -1};
+  static constexpr int cz[27] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1,
+                                 1, 1, -1, -1, 1, 1, -1, -1, 1, 1, -1, 1, -1};
+  static constexpr double w(int i) {
+    return i == 0 ? 8.0 / 27.0 : (i <= 6 ? 2.0 / 27.0 : (i <= 18 ? 1.0 / 54.0 : 1.0 / 216.0));
+  }
+};
+
+// Opposite direction: pairs are stored as (odd, even) neighbours.
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+// ---------------------------------------------------------------------------
+// Storage formats of the PDF-list.  load() returns the deviation
+// d = f - w from the rest weight in the compute type R; store() encodes a
+// deviation.  Deviation ("zero-centred") storage keeps the small signal
+// (u ~ 1e-3 .. 1e-1, F ~ 1e-6) away from the O(w) offset, which is what lets
+// 16-bit storage work at all.
+// ---------------------------------------------------------------------------
+enum StoreKind { ST_F64 = 0, ST_F32 = 1, ST_F16DEV = 2, ST_BF16DEV = 3, ST_F32DEV = 4 };
+
+template <int S>
+struct Store;
+
+template <>
+struct Store<ST_F64> {
+  using T = double;
+  using R = double;
+  __device__ static R load(T v, R w, R) { return v - w; }
+  __device__ static T store(R d, R w, R) { return w + d; }
+};
+
+template <>
+struct Store<ST_F32> {
+  using T = float;
+  using R = float;
+  __device__ static R load(T v, R w, R) { return v - w; }
+  __device__ static T store(R d, R w, R) { return w + d; }
+};
+
+template <>
+struct Store<ST_F32DEV> {
+  using T = float;
+  using R = float;
+  __device__ static R load(T v, R, R) { return v; }
+  __device__ static T store(R d, R, R) { return d; }
+};
+
+template <>
+struct Store<ST_F16DEV> {
+  using T = uint16_t;
+  using R = float;
+  // scale = 2^dev_exp (exact power of two); conversion rounds to nearest even.
+  __device__ static R load(T v, R, R inv_scale) {
+    return static_cast<float>(__builtin_bit_cast(_Float16, v)) * inv_scale;
+  }
+  __device__ static T store(R d, R, R scale) {
+    return __builtin_bit_cast(uint16_t, static_cast<_Float16>(d * scale));
+  }
+};
+
+template <>
+struct Store<ST_BF16DEV> {
+  using T = uint16_t;
+  using R = float;
+  __device__ static R load(T v, R, R inv_scale) {
+    return __uint_as_float(static_cast<uint32_t>(v) << 16) * inv_scale;
+  }
+  // float -> bfloat16, round to nearest, ties to even (NaN kept quiet).
+  __device__ static T store(R d, R, R scale) {
+    uint32_t u = __float_as_uint(d * scale);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<T>((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return static_cast<T>(u >> 16);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Launch arguments.  One launch advances up to kMaxSeg independent solves
+// ("segments"); segment s owns workgroup tiles [tile0_s, tile0_{s+1}).
+// ---------------------------------------------------------------------------
+constexpr int kMaxSeg = 16;
+
+struct Seg {
+  void* pdf;             // PDF-list of this solve
+  const int32_t* idx;    // index-list (odd steps)
+  uint32_t S;            // stride
+  uint32_t nf;           // fluid cells
+  uint32_t tile0;        // first tile of this segment in the launch
+  uint32_t pad;
+  double om1;            // SRT omega / TRT omega+ / cumulant shear rate
+  double om2;            // TRT omega- / cumulant bulk rate
+  double F[3];           // body force
+  float scale;           // 2^dev_exp (16-bit storage)
+  float inv_scale;       // 2^-dev_exp
+};
+
+struct StepArgs {
+  int32_t nseg;
+  uint32_t ntiles;
+  int32_t xcd_remap;
+  int32_t pad;
+  Seg seg[kMaxSeg];
+};
+
+// XCD-aware tile order.  Workgroups are dispatched round-robin over the 8
+// XCDs (workgroup v runs on XCD v % 8); mapping the workgroups of one XCD to
+// one contiguous range of tiles keeps neighbouring tiles (and therefore the
+// neighbour gathers of the odd step) inside one XCD's L2.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t v, uint32_t n) {
+  const uint32_t x = v & 7u, local = v >> 3;
+  const uint32_t per = n >> 3, rem = n & 7u;
+  return x * per + (x < rem ? x : rem) + local;
+}
+
+__device__ __forceinline__ int seg_of(const StepArgs& a, uint32_t tile) {
+  int s = 0;
+  for (int j = 1; j < a.nseg; ++j)
+    if (a.seg[j].tile0 <= tile) s = j;
+  return s;
+}
+
+}  // namespace lbm

@@ -1,0 +1,110 @@
+// Fused AA stream-collide kernels over the compacted fluid list
+// (Section "In-place Streaming: AA Pattern").
+//
+// odd step  (t even): for cell k, population i >= 1 is gathered from
+//   pos_i = index[(i-1)*S + k] (the upstream cell's slot, or the cell's own
+//   opposite slot where the upstream cell is not fluid); after the
+//   collision the opposite result f*_opp(i) is written back to pos_i, so
+//   every slot is read and written by exactly one thread (the index-list
+//   is a permutation of the slots) and one array suffices.
+// even step (t odd): population i is read from the cell's own slot
+//   opp(i)*S + k and f*_i is written to i*S + k -- purely local, no index
+//   reads, fully coalesced.
+//
+// One thread updates one fluid cell; a workgroup covers BLOCK consecutive
+// cells of one segment (solve).  Consecutive cells are consecutive along the
+// Morton curve, so the gathers of a wavefront stay within a few cache lines
+// per direction.
+#pragma once
+
+#include "cumulant.hpp"
+
+namespace lbm {
+
+template <int Q, int COLL, class R>
+__device__ __forceinline__ void collide(R (&d)[Q], const CollParams<R>& p) {
+  if constexpr (COLL == COLL_SRT) {
+    collide_srt<Q, R>(d, p);
+  } else if constexpr (COLL == COLL_TRT) {
+    collide_trt<Q, R>(d, p);
+  } else if constexpr (COLL == COLL_CUMULANT) {
+    static_assert(Q == 27, "cumulant needs D3Q27");
+    collide_cumulant<R>(d, p);
+  }
+}
+
+template <class R>
+__device__ __forceinline__ CollParams<R> seg_params(const Seg& g) {
+  CollParams<R> p;
+  p.om1 = R(g.om1);
+  p.om2 = R(g.om2);
+  p.Fx = R(g.F[0]);
+  p.Fy = R(g.F[1]);
+  p.Fz = R(g.F[2]);
+  return p;
+}
+
+template <int Q, int COLL, int ST, bool ODD>
+__global__ __launch_bounds__(256) void k_aa_step(const StepArgs a) {
+  using SP = Store<ST>;
+  using T = typename SP::T;
+  using R = typename SP::R;
+  const uint32_t tile = a.xcd_remap ? xcd_tile(blockIdx.x, a.ntiles) : blockIdx.x;
+  const int s = seg_of(a, tile);
+  const Seg& g = a.seg[s];
+  const uint32_t k = (tile - g.tile0) * blockDim.x + threadIdx.x;
+  if (k >= g.nf) return;
+  T* __restrict__ pdf = static_cast<T*>(g.pdf);
+  const uint32_t S = g.S;
+  const R sc = R(g.scale), isc = R(g.inv_scale);
+  R d[Q];
+  if constexpr (ODD) {
+    const int32_t* __restrict__ idx = g.idx;
+    uint32_t pos[Q];
+    pos[0] = k;
+#pragma unroll
+    for (int i = 1; i < Q; ++i)
+      pos[i] = static_cast<uint32_t>(__builtin_nontemporal_load(idx + (size_t)(i - 1) * S + k));
+#pragma unroll
+    for (int i = 0; i < Q; ++i) d[i] = SP::load(pdf[pos[i]], R(Lattice<Q>::w(i)), isc);
+    collide<Q, COLL, R>(d, seg_params<R>(g));
+#pragma unroll
+    for (int i = 0; i < Q; ++i) pdf[pos[i]] = SP::store(d[opp(i)], R(Lattice<Q>::w(i)), sc);
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      d[i] = SP::load(__builtin_nontemporal_load(pdf + (size_t)opp(i) * S + k),
+                      R(Lattice<Q>::w(i)), isc);
+    collide<Q, COLL, R>(d, seg_params<R>(g));
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      __builtin_nontemporal_store(SP::store(d[i], R(Lattice<Q>::w(i)), sc),
+                                  pdf + (size_t)i * S + k);
+  }
+}
+
+// Host-side dispatch over (collision, storage, parity) for one Q.
+template <int Q, int COLL, int ST>
+inline hipError_t launch_aa_cs(bool odd, const StepArgs& a, int block, hipStream_t st) {
+  dim3 grid(a.ntiles), blk(block);
+  if (odd)
+    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, true>), grid, blk, 0, st, a);
+  else
+    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, false>), grid, blk, 0, st, a);
+  return hipGetLastError();
+}
+
+template <int Q, int COLL>
+inline hipError_t launch_aa_c(int storage, bool odd, const StepArgs& a, int block,
+                              hipStream_t st) {
+  switch (storage) {
+    case ST_F64: return launch_aa_cs<Q, COLL, ST_F64>(odd, a, block, st);
+    case ST_F32: return launch_aa_cs<Q, COLL, ST_F32>(odd, a, block, st);
+    case ST_F16DEV: return launch_aa_cs<Q, COLL, ST_F16DEV>(odd, a, block, st);
+    case ST_BF16DEV: return launch_aa_cs<Q, COLL, ST_BF16DEV>(odd, a, block, st);
+    case ST_F32DEV: return launch_aa_cs<Q, COLL, ST_F32DEV>(odd, a, block, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace lbm

@@ -1,0 +1,18 @@
+// AA step kernels, D3Q27 (SRT, TRT, cumulant; all storages).
+#include "internal.hpp"
+#include "step_impl.hpp"
+
+namespace lbm {
+
+hipError_t launch_aa_q27(int coll, int storage, bool odd, const StepArgs& a, int block,
+                         hipStream_t st) {
+  switch (coll) {
+    case COLL_NONE: return launch_aa_c<27, COLL_NONE>(storage, odd, a, block, st);
+    case COLL_SRT: return launch_aa_c<27, COLL_SRT>(storage, odd, a, block, st);
+    case COLL_TRT: return launch_aa_c<27, COLL_TRT>(storage, odd, a, block, st);
+    case COLL_CUMULANT: return launch_aa_c<27, COLL_CUMULANT>(storage, odd, a, block, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace lbm

@@ -1,0 +1,408 @@
+"""Thin Python binding of liblbm.so (the C-ABI declared in include/lbm.h).
+
+The functions named ``lbm_*`` marshal arguments onto the C entry points of
+the same name and raise ``LbmError`` on a non-zero status.  Every step of the
+sparse AA path runs in the library's HIP kernels; PyTorch only provides
+device memory (``tensor.data_ptr()``) and the stream
+(``torch.cuda.current_stream().cuda_stream``).  There is no CPU fallback: if
+the library is missing or cannot be loaded, importing this module raises.
+
+The helper classes ``SparseDomain``/``Solver`` and ``DenseSolver`` allocate
+the device buffers a caller needs and drive the entry points.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblbm.so")
+
+# ----------------------------------------------------------------- constants
+LBM_OK, LBM_EINVAL, LBM_ERANGE, LBM_ENOMEM = 0, -1, -2, -3
+LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = -4, -5, -6
+D3Q19, D3Q27 = 19, 27
+COLL_NONE, COLL_SRT, COLL_TRT, COLL_CUMULANT = 0, 1, 2, 3
+STORE_F64, STORE_F32, STORE_F16DEV, STORE_BF16DEV, STORE_F32DEV = 0, 1, 2, 3, 4
+ORDER_MORTON, ORDER_LEX = 0, 1
+BC_NOSLIP, BC_UBB, BC_PRESSURE = 0, 1, 2
+KERNEL_ODD, KERNEL_EVEN, KERNEL_DENSE = 0, 1, 2
+
+STORE_BYTES = {STORE_F64: 8, STORE_F32: 4, STORE_F16DEV: 2, STORE_BF16DEV: 2, STORE_F32DEV: 4}
+STORE_NAMES = {STORE_F64: "f64", STORE_F32: "f32", STORE_F16DEV: "f16dev",
+               STORE_BF16DEV: "bf16dev", STORE_F32DEV: "f32dev"}
+
+_i32, _i64, _u32, _u64, _f64 = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                ctypes.c_uint64, ctypes.c_double)
+_vp = ctypes.c_void_p
+
+
+class lbm_layout(ctypes.Structure):
+    _fields_ = [("nx", _i32), ("ny", _i32), ("nz", _i32), ("periodic", _u32), ("q", _i32),
+                ("order", _i32), ("align", _i32), ("reserved", _i32), ("n_fluid", _i64),
+                ("stride", _i64), ("n_links", _i64)]
+
+
+class lbm_state(ctypes.Structure):
+    _fields_ = [("layout", lbm_layout), ("storage", _i32), ("dev_exp", _i32), ("pdf", _vp),
+                ("index", _vp), ("links", _vp), ("t", _i64)]
+
+
+class lbm_collision(ctypes.Structure):
+    _fields_ = [("kind", _i32), ("reserved", _i32), ("tau", _f64), ("magic", _f64),
+                ("omega_bulk", _f64), ("force", _f64 * 3)]
+
+
+class lbm_bclass(ctypes.Structure):
+    _fields_ = [("type", _i32), ("reserved", _i32), ("u", _f64 * 3), ("rho", _f64)]
+
+
+class lbm_bspec(ctypes.Structure):
+    _fields_ = [("n_classes", _i32), ("reserved", _i32), ("cls", lbm_bclass * 8)]
+
+
+class lbm_reduction(ctypes.Structure):
+    _fields_ = [("mass", _f64), ("mom", _f64 * 3), ("n_fluid", _i64), ("finite", _i32),
+                ("reserved", _i32)]
+
+
+class lbm_dense_state(ctypes.Structure):
+    _fields_ = [("nx", _i32), ("ny", _i32), ("nz", _i32), ("periodic", _u32), ("q", _i32),
+                ("storage", _i32), ("dev_exp", _i32), ("reserved", _i32), ("pdf", _vp),
+                ("mask", _vp), ("t", _i64)]
+
+
+class lbm_launch(ctypes.Structure):
+    _fields_ = [("block", _i32), ("xcd_remap", _i32), ("reserved", _i32 * 2)]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, fn, code, msg):
+        super().__init__(f"{fn} failed with status {code}: {msg}")
+        self.code = code
+
+
+_lock = threading.Lock()
+_lib = None
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "lbm_abi_version": (_i32, []),
+    "lbm_last_error": (ctypes.c_char_p, []),
+    "lbm_build_workspace_bytes": (_u64, [_i32, _i32, _i32, _i32]),
+    "lbm_build_sparse": (_i32, [_vp, _i32, _i32, _i32, _u32, _i32, _i32, _i32, _vp,
+                                ctypes.POINTER(lbm_layout), _vp, _vp, _vp, _vp]),
+    "lbm_init_equilibrium": (_i32, [ctypes.POINTER(lbm_state), _f64, ctypes.POINTER(_f64), _vp]),
+    "lbm_step": (_i32, [ctypes.POINTER(lbm_state), _i32, ctypes.POINTER(lbm_collision),
+                        ctypes.POINTER(lbm_bspec), _vp]),
+    "lbm_moments": (_i32, [ctypes.POINTER(lbm_state), ctypes.POINTER(lbm_collision), _i32, _vp,
+                           _vp, _vp]),
+    "lbm_reduce_workspace_bytes": (_u64, [ctypes.POINTER(lbm_layout)]),
+    "lbm_reduce": (_i32, [ctypes.POINTER(lbm_state), ctypes.POINTER(lbm_collision), _vp,
+                          ctypes.POINTER(lbm_reduction), _vp]),
+    "lbm_step_batch": (_i32, [ctypes.POINTER(ctypes.POINTER(lbm_state)),
+                              ctypes.POINTER(ctypes.POINTER(lbm_collision)),
+                              ctypes.POINTER(ctypes.POINTER(lbm_bspec)), _i32, _i32, _vp]),
+    "lbm_reduce_batch": (_i32, [ctypes.POINTER(ctypes.POINTER(lbm_state)),
+                                ctypes.POINTER(ctypes.POINTER(lbm_collision)), _i32, _vp,
+                                ctypes.POINTER(lbm_reduction), _vp]),
+    "lbm_dense_build_mask": (_i32, [_vp, _i32, _i32, _i32, _u32, _i32, _vp, _vp]),
+    "lbm_dense_init_equilibrium": (_i32, [ctypes.POINTER(lbm_dense_state), _f64,
+                                          ctypes.POINTER(_f64), _vp]),
+    "lbm_dense_step": (_i32, [ctypes.POINTER(lbm_dense_state), _i32,
+                              ctypes.POINTER(lbm_collision), _vp]),
+    "lbm_set_launch": (_i32, [_i32, _i32, _i32, ctypes.POINTER(lbm_launch)]),
+    "lbm_get_launch": (_i32, [_i32, _i32, _i32, ctypes.POINTER(lbm_launch)]),
+    "lbm_copy": (_i32, [_vp, _vp, _u64, _vp]),
+}
+
+EXPORTED = tuple(_SIGS)
+
+
+def load():
+    """Load liblbm.so (raises if it is missing: there is no fallback path)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              f"`python -m paper_2408_06880_amd.build` (hipcc, gfx950)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+        return lib
+
+
+def _call(name, *args):
+    lib = load()
+    rc = getattr(lib, name)(*args)
+    if rc != 0:
+        msg = lib.lbm_last_error()
+        raise LbmError(name, rc, msg.decode() if msg else "")
+    return rc
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return _vp(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return _vp(stream)
+    return _vp(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else _vp(t.data_ptr())
+
+
+# ------------------------------------------------------ C entry points
+def lbm_abi_version():
+    return load().lbm_abi_version()
+
+
+def lbm_last_error():
+    m = load().lbm_last_error()
+    return m.decode() if m else ""
+
+
+def lbm_build_workspace_bytes(nx, ny, nz, order=ORDER_MORTON):
+    return int(load().lbm_build_workspace_bytes(nx, ny, nz, order))
+
+
+def lbm_build_sparse(labels, nx, ny, nz, periodic, q, order, align, workspace, layout=None,
+                     cells=None, index=None, links=None, stream=None):
+    """Plan (cells None: returns a new lbm_layout) or fill (writes cells/index/links)."""
+    lay = layout if layout is not None else lbm_layout()
+    _call("lbm_build_sparse", _ptr(labels), nx, ny, nz, periodic, q, order, align,
+          _ptr(workspace), ctypes.byref(lay), _ptr(cells), _ptr(index), _ptr(links),
+          _stream(stream))
+    return lay
+
+
+def lbm_init_equilibrium(state, rho0=1.0, u0=(0.0, 0.0, 0.0), stream=None):
+    u = (_f64 * 3)(*u0)
+    _call("lbm_init_equilibrium", ctypes.byref(state), float(rho0), u, _stream(stream))
+
+
+def lbm_step(state, n_steps, coll, bspec=None, stream=None):
+    _call("lbm_step", ctypes.byref(state), int(n_steps), ctypes.byref(coll),
+          ctypes.byref(bspec) if bspec is not None else None, _stream(stream))
+
+
+def lbm_moments(state, coll, out_f64, rho, u, stream=None):
+    _call("lbm_moments", ctypes.byref(state), ctypes.byref(coll), 1 if out_f64 else 0,
+          _ptr(rho), _ptr(u), _stream(stream))
+
+
+def lbm_reduce_workspace_bytes(layout):
+    return int(load().lbm_reduce_workspace_bytes(ctypes.byref(layout)))
+
+
+def lbm_reduce(state, coll, workspace, stream=None, check=True):
+    out = lbm_reduction()
+    rc = load().lbm_reduce(ctypes.byref(state), ctypes.byref(coll), _ptr(workspace),
+                           ctypes.byref(out), _stream(stream))
+    if rc != 0 and (check or rc != LBM_EUNSTABLE):
+        raise LbmError("lbm_reduce", rc, lbm_last_error())
+    return out
+
+
+def lbm_step_batch(states, colls, bspecs, n_steps, stream=None):
+    n = len(states)
+    sp = (ctypes.POINTER(lbm_state) * n)(*[ctypes.pointer(s) for s in states])
+    cp = (ctypes.POINTER(lbm_collision) * n)(*[ctypes.pointer(c) for c in colls])
+    bp = None
+    if bspecs is not None:
+        bp = (ctypes.POINTER(lbm_bspec) * n)(
+            *[ctypes.pointer(b) if b is not None else ctypes.POINTER(lbm_bspec)() for b in bspecs])
+    _call("lbm_step_batch", sp, cp, bp, n, int(n_steps), _stream(stream))
+
+
+def lbm_reduce_batch(states, colls, workspace, stream=None, check=True):
+    n = len(states)
+    sp = (ctypes.POINTER(lbm_state) * n)(*[ctypes.pointer(s) for s in states])
+    cp = (ctypes.POINTER(lbm_collision) * n)(*[ctypes.pointer(c) for c in colls])
+    out = (lbm_reduction * n)()
+    rc = load().lbm_reduce_batch(sp, cp, n, _ptr(workspace), out, _stream(stream))
+    if rc != 0 and (check or rc != LBM_EUNSTABLE):
+        raise LbmError("lbm_reduce_batch", rc, lbm_last_error())
+    return list(out)
+
+
+def lbm_dense_build_mask(labels, nx, ny, nz, periodic, q, mask, stream=None):
+    _call("lbm_dense_build_mask", _ptr(labels), nx, ny, nz, periodic, q, _ptr(mask),
+          _stream(stream))
+
+
+def lbm_dense_init_equilibrium(state, rho0=1.0, u0=(0.0, 0.0, 0.0), stream=None):
+    u = (_f64 * 3)(*u0)
+    _call("lbm_dense_init_equilibrium", ctypes.byref(state), float(rho0), u, _stream(stream))
+
+
+def lbm_dense_step(state, n_steps, coll, stream=None):
+    _call("lbm_dense_step", ctypes.byref(state), int(n_steps), ctypes.byref(coll),
+          _stream(stream))
+
+
+def lbm_set_launch(kernel, q, storage, block=256, xcd_remap=1):
+    cfg = lbm_launch(block, xcd_remap)
+    _call("lbm_set_launch", kernel, q, storage, ctypes.byref(cfg))
+
+
+def lbm_get_launch(kernel, q, storage):
+    cfg = lbm_launch()
+    _call("lbm_get_launch", kernel, q, storage, ctypes.byref(cfg))
+    return cfg.block, cfg.xcd_remap
+
+
+def lbm_copy(dst, src, nbytes, stream=None):
+    _call("lbm_copy", _ptr(dst), _ptr(src), int(nbytes), _stream(stream))
+
+
+# ------------------------------------------------------- conveniences
+def collision(kind=COLL_TRT, tau=0.8, magic=3.0 / 16.0, omega_bulk=1.0, force=(0.0, 0.0, 0.0)):
+    c = lbm_collision()
+    c.kind, c.tau, c.magic, c.omega_bulk = kind, tau, magic, omega_bulk
+    for a in range(3):
+        c.force[a] = float(force[a])
+    return c
+
+
+def bspec(classes=()):
+    """classes: sequence of (type, (ux, uy, uz), rho) for labels 2, 3, ..."""
+    b = lbm_bspec()
+    b.n_classes = len(classes)
+    for i, (typ, u, rho) in enumerate(classes):
+        b.cls[i].type = typ
+        for a in range(3):
+            b.cls[i].u[a] = float(u[a])
+        b.cls[i].rho = float(rho)
+    return b
+
+
+def _torch_storage_dtype(storage):
+    import torch
+    return {STORE_F64: torch.float64, STORE_F32: torch.float32, STORE_F16DEV: torch.int16,
+            STORE_BF16DEV: torch.int16, STORE_F32DEV: torch.float32}[storage]
+
+
+class SparseDomain:
+    """Fluid list, index-list and boundary links of one geometry (device)."""
+
+    def __init__(self, labels, periodic, q=19, order=ORDER_MORTON, align=64, stream=None,
+                 device="cuda"):
+        import numpy as np
+        import torch
+        lab = labels
+        if isinstance(lab, np.ndarray):
+            lab = torch.from_numpy(np.ascontiguousarray(lab, dtype=np.uint8))
+        lab = lab.to(device=device, dtype=torch.uint8).contiguous()
+        nz, ny, nx = lab.shape
+        ws = torch.empty(lbm_build_workspace_bytes(nx, ny, nz, order), dtype=torch.uint8,
+                         device=device)
+        lay = lbm_build_sparse(lab, nx, ny, nz, periodic, q, order, align, ws, stream=stream)
+        self.cells = torch.empty(max(lay.n_fluid, 1), dtype=torch.int32, device=device)
+        self.index = torch.empty(max((q - 1) * lay.stride, 1), dtype=torch.int32, device=device)
+        self.links = torch.empty(max(2 * lay.n_links, 2), dtype=torch.int32, device=device)
+        lbm_build_sparse(lab, nx, ny, nz, periodic, q, order, align, ws, layout=lay,
+                         cells=self.cells, index=self.index,
+                         links=self.links if lay.n_links else None, stream=stream)
+        self.layout = lay
+        self.shape = (nz, ny, nx)
+        self.q = q
+        self.periodic = periodic
+        del ws
+
+    @property
+    def n_fluid(self):
+        return int(self.layout.n_fluid)
+
+    @property
+    def stride(self):
+        return int(self.layout.stride)
+
+    @property
+    def n_links(self):
+        return int(self.layout.n_links)
+
+
+class Solver:
+    """One sparse AA solve: PDF-list on the device plus its lbm_state."""
+
+    def __init__(self, domain: SparseDomain, storage=STORE_F32, dev_exp=0, device="cuda"):
+        import torch
+        self.domain = domain
+        n = domain.q * domain.stride
+        self.pdf = torch.empty(max(n, 1), dtype=_torch_storage_dtype(storage), device=device)
+        st = lbm_state()
+        st.layout = domain.layout
+        st.storage = storage
+        st.dev_exp = dev_exp
+        st.pdf = self.pdf.data_ptr()
+        st.index = domain.index.data_ptr()
+        st.links = domain.links.data_ptr() if domain.n_links else None
+        st.t = 0
+        self.state = st
+        self.storage = storage
+        self._red_ws = torch.empty(lbm_reduce_workspace_bytes(domain.layout), dtype=torch.uint8,
+                                   device=device)
+
+    @property
+    def t(self):
+        return int(self.state.t)
+
+    def init(self, rho0=1.0, u0=(0.0, 0.0, 0.0), stream=None):
+        lbm_init_equilibrium(self.state, rho0, u0, stream)
+
+    def step(self, n, coll, bs=None, stream=None):
+        lbm_step(self.state, n, coll, bs, stream)
+
+    def moments(self, coll, f64=True, stream=None):
+        import torch
+        dt = torch.float64 if f64 else torch.float32
+        S = max(self.domain.stride, 1)
+        rho = torch.empty(S, dtype=dt, device=self.pdf.device)
+        u = torch.empty(3 * S, dtype=dt, device=self.pdf.device)
+        lbm_moments(self.state, coll, f64, rho, u, stream)
+        return rho, u.view(3, S)
+
+    def reduce(self, coll, stream=None, check=True):
+        return lbm_reduce(self.state, coll, self._red_ws, stream, check)
+
+
+class DenseSolver:
+    """Dense direct-addressing AA comparator over every box cell."""
+
+    def __init__(self, labels, periodic, q=19, storage=STORE_F32, dev_exp=0, device="cuda",
+                 stream=None):
+        import numpy as np
+        import torch
+        lab = labels
+        if isinstance(lab, np.ndarray):
+            lab = torch.from_numpy(np.ascontiguousarray(lab, dtype=np.uint8))
+        lab = lab.to(device=device, dtype=torch.uint8).contiguous()
+        nz, ny, nx = lab.shape
+        N = nx * ny * nz
+        self.mask = torch.empty(N, dtype=torch.int32, device=device)
+        lbm_dense_build_mask(lab, nx, ny, nz, periodic, q, self.mask, stream)
+        self.pdf = torch.empty(q * N, dtype=_torch_storage_dtype(storage), device=device)
+        st = lbm_dense_state()
+        st.nx, st.ny, st.nz, st.periodic, st.q = nx, ny, nz, periodic, q
+        st.storage, st.dev_exp = storage, dev_exp
+        st.pdf = self.pdf.data_ptr()
+        st.mask = self.mask.data_ptr()
+        st.t = 0
+        self.state = st
+        self.shape = (nz, ny, nx)
+        self.q = q
+
+    def init(self, rho0=1.0, u0=(0.0, 0.0, 0.0), stream=None):
+        lbm_dense_init_equilibrium(self.state, rho0, u0, stream)
+
+    def step(self, n, coll, stream=None):
+        lbm_dense_step(self.state, n, coll, stream)

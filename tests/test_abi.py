@@ -1,0 +1,99 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every function
+include/lbm.h declares, and rejects invalid arguments before touching the
+GPU (host-only paths; no compute call is made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2408_06880_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(lbm.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = lbm.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert lbm.lbm_abi_version() == 1
+
+
+def test_struct_sizes_match_header_layout():
+    assert ctypes.sizeof(lbm.lbm_layout) == 56
+    assert ctypes.sizeof(lbm.lbm_state) == 56 + 8 + 24 + 8
+    assert ctypes.sizeof(lbm.lbm_collision) == 8 + 8 * 6
+    assert ctypes.sizeof(lbm.lbm_bspec) == 8 + 8 * 40
+    assert ctypes.sizeof(lbm.lbm_reduction) == 48
+    assert ctypes.sizeof(lbm.lbm_dense_state) == 32 + 16 + 8
+
+
+def test_workspace_queries():
+    assert lbm.lbm_build_workspace_bytes(0, 4, 4) == 0
+    assert lbm.lbm_build_workspace_bytes(2000, 4, 4) == 0
+    n = lbm.lbm_build_workspace_bytes(32, 32, 32, lbm.ORDER_MORTON)
+    assert n >= 4 * 32 ** 3
+    lay = lbm.lbm_layout()
+    lay.n_fluid = 1000
+    assert lbm.lbm_reduce_workspace_bytes(lay) >= 4 * 5 * 8
+
+
+def _fake_state(q=19, nf=100, S=128, storage=lbm.STORE_F32):
+    st = lbm.lbm_state()
+    st.layout.q = q
+    st.layout.n_fluid = nf
+    st.layout.stride = S
+    st.storage = storage
+    st.pdf = 16   # never dereferenced: validation fails first
+    st.index = 16
+    return st
+
+
+def expect(code, fn, *args):
+    with pytest.raises(lbm.LbmError) as e:
+        fn(*args)
+    assert e.value.code == code
+
+
+def test_invalid_arguments_rejected_on_host():
+    coll_bad = lbm.collision(lbm.COLL_SRT, tau=0.5)
+    expect(lbm.LBM_EINVAL, lbm.lbm_step, _fake_state(), 1, coll_bad, None, 0)
+    expect(lbm.LBM_EINVAL, lbm.lbm_step, _fake_state(q=19), 1,
+           lbm.collision(lbm.COLL_CUMULANT, tau=0.8), None, 0)
+    expect(lbm.LBM_EINVAL, lbm.lbm_step, _fake_state(storage=9), 1, lbm.collision(), None, 0)
+    st = _fake_state(storage=lbm.STORE_F16DEV)
+    st.dev_exp = 30
+    expect(lbm.LBM_EINVAL, lbm.lbm_step, st, 1, lbm.collision(), None, 0)
+    big = _fake_state(nf=200_000_000, S=200_000_000)
+    expect(lbm.LBM_ERANGE, lbm.lbm_step, big, 1, lbm.collision(), None, 0)
+    expect(lbm.LBM_EINVAL, lbm.lbm_step, _fake_state(), -1, lbm.collision(), None, 0)
+    expect(lbm.LBM_EINVAL, lbm.lbm_set_launch, lbm.KERNEL_ODD, 19, lbm.STORE_F32, 100, 1)
+    expect(lbm.LBM_EINVAL, lbm.lbm_set_launch, 7, 19, lbm.STORE_F32, 256, 1)
+
+
+def test_batch_mismatch_rejected_on_host():
+    a = _fake_state(storage=lbm.STORE_F32)
+    b = _fake_state(storage=lbm.STORE_F64)
+    c = lbm.collision()
+    expect(lbm.LBM_ESTATE, lbm.lbm_step_batch, [a, b], [c, c], None, 1, 0)
+    b = _fake_state(storage=lbm.STORE_F32)
+    b.t = 1
+    expect(lbm.LBM_ESTATE, lbm.lbm_step_batch, [a, b], [c, c], None, 1, 0)
+
+
+def test_launch_table_roundtrip():
+    old = lbm.lbm_get_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F16DEV)
+    lbm.lbm_set_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F16DEV, 128, 0)
+    assert lbm.lbm_get_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F16DEV) == (128, 0)
+    lbm.lbm_set_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F16DEV, *old)
