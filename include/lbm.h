@@ -73,7 +73,12 @@ enum {
   LBM_STORE_BF16DEV = 3, /* bfloat16 (f_i - w_i) * 2^dev_exp                      */
   LBM_STORE_F32DEV = 4   /* float (f_i - w_i)                                     */
 };
-enum { LBM_ORDER_MORTON = 0, LBM_ORDER_LEX = 1 };
+/* Fluid-cell order of the lists.  MORTON: Morton key of (x, y, z), bit b of
+ * x, y, z at bits 3b, 3b+1, 3b+2.  LEX: linear id.  BLOCKED: the box is cut
+ * into blocks of nx * 8 * 8 cells (whole x rows, 8 in y, 8 in z); blocks are
+ * visited in 2-D Morton order of (y/8, z/8) (y bit at 2b, z bit at 2b+1)
+ * and cells inside a block lexicographically (x, then y, then z). */
+enum { LBM_ORDER_MORTON = 0, LBM_ORDER_LEX = 1, LBM_ORDER_BLOCKED = 2 };
 enum { LBM_BC_NOSLIP = 0, LBM_BC_UBB = 1, LBM_BC_PRESSURE = 2 };
 
 /* Sizes of one sparse domain.  Filled by lbm_build_sparse (plan call). */
@@ -104,8 +109,7 @@ uint64_t lbm_build_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t o
 
 /* Two-phase build.
  *  labels     device, uint8[nx*ny*nz] (layout above); nx, ny, nz in [1, 1024].
- *  order      LBM_ORDER_MORTON (fluid cells sorted by Morton key, bit b of
- *             x, y, z at bits 3b, 3b+1, 3b+2) or LBM_ORDER_LEX (by lin).
+ *  order      LBM_ORDER_MORTON, LBM_ORDER_LEX or LBM_ORDER_BLOCKED (above).
  *  align      stride multiple, >= 1 (64 recommended).
  *  workspace  device, >= lbm_build_workspace_bytes(nx, ny, nz, order).
  *  layout     host.  PLAN call (cells == NULL): SYNC; fills *layout; index

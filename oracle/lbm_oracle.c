@@ -508,6 +508,19 @@ uint64_t orc_morton_key(uint32_t x, uint32_t y, uint32_t z) {
   return key;
 }
 
+/* Blocked order: blocks of nx*8*8 cells (whole x rows), visited in 2-D
+ * Morton order of (y/8, z/8) with y at bit 2b and z at bit 2b+1; inside a
+ * block x fastest, then y, then z. */
+uint64_t orc_blocked_key(uint32_t x, uint32_t y, uint32_t z, uint32_t nx) {
+  uint32_t ty = y / 8, tz = z / 8, ly = y % 8, lz = z % 8;
+  uint64_t t = 0;
+  for (int b = 0; b < 16; ++b) {
+    t |= (uint64_t)((ty >> b) & 1u) << (2 * b);
+    t |= (uint64_t)((tz >> b) & 1u) << (2 * b + 1);
+  }
+  return t * ((uint64_t)nx * 64) + x + (uint64_t)nx * (ly + 8 * lz);
+}
+
 typedef struct {
   uint64_t key;
   int64_t lin;
@@ -523,7 +536,7 @@ static int orc_keyed_cmp(const void* a, const void* b) {
 
 /* Sparse list construction (Section "Sparse Data Structure"):
  *   cells[k]          linear id of the k-th fluid cell (order 0: Morton,
- *                     order 1: ascending linear id);
+ *                     order 1: ascending linear id, order 2: blocked);
  *   index[(i-1)*S+k]  for direction i >= 1, the PDF-list position cell k
  *                     pulls population i from: i*S + m when the upstream
  *                     cell x_k - c_i is fluid with list index m, otherwise
@@ -537,7 +550,7 @@ int orc_sparse_build(const uint8_t* labels, int nx, int ny, int nz, uint32_t per
                      int order, int align, int64_t* n_fluid, int64_t* stride, int64_t* n_links,
                      int32_t* cells, int32_t* index, int32_t* links) {
   orc_stencil s;
-  if (orc_stencil_init(&s, q) || align < 1) return -1;
+  if (orc_stencil_init(&s, q) || align < 1 || order < 0 || order > 2) return -1;
   const int64_t N = (int64_t)nx * ny * nz;
   int64_t nf = 0;
   for (int64_t lin = 0; lin < N; ++lin) nf += labels[lin] == 0;
@@ -574,8 +587,10 @@ int orc_sparse_build(const uint8_t* labels, int nx, int ny, int nz, uint32_t per
         int64_t lin = (int64_t)x + (int64_t)nx * ((int64_t)y + (int64_t)ny * z);
         if (labels[lin] != 0) continue;
         kv[k].lin = lin;
-        kv[k].key = order == 0 ? orc_morton_key((uint32_t)x, (uint32_t)y, (uint32_t)z)
-                               : (uint64_t)lin;
+        kv[k].key = order == 0   ? orc_morton_key((uint32_t)x, (uint32_t)y, (uint32_t)z)
+                    : order == 2 ? orc_blocked_key((uint32_t)x, (uint32_t)y, (uint32_t)z,
+                                                   (uint32_t)nx)
+                                 : (uint64_t)lin;
         ++k;
       }
   qsort(kv, (size_t)nf, sizeof(orc_keyed), orc_keyed_cmp);

@@ -45,11 +45,13 @@ bool g_launch_init = false;
 
 void launch_defaults() {
   if (g_launch_init) return;
-  for (auto& a : g_launch)
-    for (auto& b : a)
+  // Measured on MI355X: the gather/scatter (odd) kernel gains from keeping
+  // neighbouring tiles on one XCD; the streaming kernels do not.
+  for (int k = 0; k < 3; ++k)
+    for (auto& b : g_launch[k])
       for (auto& c : b) {
         c.block = 256;
-        c.xcd_remap = 1;
+        c.xcd_remap = (k == LBM_KERNEL_ODD) ? 1 : 0;
         c.reserved[0] = c.reserved[1] = 0;
       }
   g_launch_init = true;
@@ -209,13 +211,20 @@ static void build_plan(int32_t nx, int32_t ny, int32_t nz, int32_t order, uint32
                        uint64_t& n_codes, uint32_t& n_chunks) {
   const int32_t m = nx > ny ? (nx > nz ? nx : nz) : (ny > nz ? ny : nz);
   bits = 0;
-  while ((1 << bits) < m) ++bits;
-  n_codes = order == LBM_ORDER_MORTON ? (uint64_t)1 << (3 * bits) : (uint64_t)nx * ny * nz;
+  if (order == LBM_ORDER_BLOCKED) {
+    const int32_t by = (ny + kBlockYZ - 1) / kBlockYZ, bz = (nz + kBlockYZ - 1) / kBlockYZ;
+    const int32_t mb = by > bz ? by : bz;
+    while ((1 << bits) < mb) ++bits;
+    n_codes = ((uint64_t)1 << (2 * bits)) * (uint64_t)nx * (kBlockYZ * kBlockYZ);
+  } else {
+    while ((1 << bits) < m) ++bits;
+    n_codes = order == LBM_ORDER_MORTON ? (uint64_t)1 << (3 * bits) : (uint64_t)nx * ny * nz;
+  }
   n_chunks = ceil_div(n_codes, kChunk);
 }
 
 uint64_t lbm_build_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t order) {
-  if (!build_dims_ok(nx, ny, nz) || (order != 0 && order != 1)) return 0;
+  if (!build_dims_ok(nx, ny, nz) || order < 0 || order > 2) return 0;
   uint32_t bits, n_chunks;
   uint64_t n_codes;
   build_plan(nx, ny, nz, order, bits, n_codes, n_chunks);
@@ -229,7 +238,7 @@ lbm_status lbm_build_sparse(const uint8_t* labels, int32_t nx, int32_t ny, int32
   if (!labels || !workspace || !layout) return fail(LBM_EINVAL, "labels/workspace/layout is NULL");
   if (!build_dims_ok(nx, ny, nz)) return fail(LBM_EINVAL, "box sizes must be in [1, 1024]");
   if (q != 19 && q != 27) return fail(LBM_EINVAL, "q must be 19 or 27");
-  if (order != LBM_ORDER_MORTON && order != LBM_ORDER_LEX) return fail(LBM_EINVAL, "bad order");
+  if (order < LBM_ORDER_MORTON || order > LBM_ORDER_BLOCKED) return fail(LBM_EINVAL, "bad order");
   if (align < 1) return fail(LBM_EINVAL, "align must be >= 1");
   if (periodic > 7u) return fail(LBM_EINVAL, "periodic must be a 3-bit mask");
   hipStream_t st = (hipStream_t)stream;

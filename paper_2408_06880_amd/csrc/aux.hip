@@ -338,30 +338,23 @@ hipError_t launch_reduce(int q, int storage, const StepArgs& a, bool odd_t, doub
 }
 
 // -------------------------------------------------------------- copy
-// Bandwidth reference: 16-byte loads and stores, 4 independent vectors in
-// flight per thread, grid-stride over the buffer.
-__global__ __launch_bounds__(256) void k_copy(const float4* __restrict__ src,
-                                              float4* __restrict__ dst, uint64_t n) {
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (; i + 3 * stride < n; i += 4 * stride) {
-    const float4 a = src[i], b = src[i + stride], c = src[i + 2 * stride],
-                 d = src[i + 3 * stride];
-    dst[i] = a;
-    dst[i + stride] = b;
-    dst[i + 2 * stride] = c;
-    dst[i + 3 * stride] = d;
-  }
-  for (; i < n; i += stride) dst[i] = src[i];
+// Bandwidth reference: one 16-byte vector per thread, non-temporal load and
+// store, one workgroup per 4 KiB.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_copy(const v4f* __restrict__ src, v4f* __restrict__ dst,
+                                              uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 hipError_t launch_copy(void* dst, const void* src, uint64_t bytes, hipStream_t st) {
   const uint64_t n = bytes / 16;
   if (n == 0) return hipSuccess;
-  uint64_t blocks = (n + 255) / 256;
-  if (blocks > 256ull * 32ull) blocks = 256ull * 32ull;
-  hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, st, (const float4*)src,
-                     (float4*)dst, n);
+  const uint64_t blocks = (n + 255) / 256;
+  if (blocks > 0x7fffffffull) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, st, (const v4f*)src,
+                     (v4f*)dst, n);
   return hipGetLastError();
 }
 

@@ -21,9 +21,30 @@ __device__ __forceinline__ uint32_t compact3(uint32_t v) {
   return v;
 }
 
+__device__ __forceinline__ uint32_t compact2(uint32_t v) {
+  // keep bits 0, 2, 4, ... of v and pack them (16 bits max)
+  v &= 0x55555555u;
+  v = (v | (v >> 1)) & 0x33333333u;
+  v = (v | (v >> 2)) & 0x0f0f0f0fu;
+  v = (v | (v >> 4)) & 0x00ff00ffu;
+  v = (v | (v >> 8)) & 0x0000ffffu;
+  return v;
+}
+
 // Decode a code into (x, y, z); false if it lies outside the box.
 __device__ __forceinline__ bool decode(const BuildArgs& b, uint64_t code, int& x, int& y,
                                        int& z) {
+  if (b.order == 2) {
+    // blocks of nx * 8 * 8 cells in 2-D Morton order of (y/8, z/8)
+    const uint64_t blk = (uint64_t)b.nx * (kBlockYZ * kBlockYZ);
+    const uint32_t t = (uint32_t)(code / blk);
+    const uint32_t local = (uint32_t)(code - (uint64_t)t * blk);
+    x = (int)(local % (uint32_t)b.nx);
+    const uint32_t r = local / (uint32_t)b.nx;
+    y = (int)(compact2(t) * kBlockYZ + r % kBlockYZ);
+    z = (int)(compact2(t >> 1) * kBlockYZ + r / kBlockYZ);
+    return y < b.ny && z < b.nz;
+  }
   if (b.order == 0) {
     const uint32_t c = (uint32_t)code;
     x = (int)compact3(c);

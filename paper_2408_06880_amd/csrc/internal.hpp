@@ -54,6 +54,7 @@ struct BuildArgs {
   uint32_t n_chunks;    // ceil(n_codes / kChunk)
 };
 constexpr int kBuildBlock = 256;
+constexpr int kBlockYZ = 8;  // y and z edge of a block in the blocked order
 constexpr int kCodesPerThread = 16;
 constexpr uint32_t kChunk = kBuildBlock * kCodesPerThread;
 // counts: uint32[2*(n_chunks+1)] (fluid cells, links per chunk -> exclusive

@@ -25,7 +25,7 @@ LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = -4, -5, -6
 D3Q19, D3Q27 = 19, 27
 COLL_NONE, COLL_SRT, COLL_TRT, COLL_CUMULANT = 0, 1, 2, 3
 STORE_F64, STORE_F32, STORE_F16DEV, STORE_BF16DEV, STORE_F32DEV = 0, 1, 2, 3, 4
-ORDER_MORTON, ORDER_LEX = 0, 1
+ORDER_MORTON, ORDER_LEX, ORDER_BLOCKED = 0, 1, 2
 BC_NOSLIP, BC_UBB, BC_PRESSURE = 0, 1, 2
 KERNEL_ODD, KERNEL_EVEN, KERNEL_DENSE = 0, 1, 2
 

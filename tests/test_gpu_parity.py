@@ -108,7 +108,9 @@ CLASSES = [(lbm.BC_UBB, (0.0, 0.0, 0.02), 1.0), (lbm.BC_PRESSURE, (0, 0, 0), 1.0
 # --------------------------------------------------------------- builder
 BUILD_CASES = [((20, 18, 17), 0.4, 7, 19, 0, 64), ((33, 9, 21), 0.3, 5, 27, 0, 1),
                ((16, 16, 16), 0.5, 0, 19, 1, 8), ((40, 3, 7), 0.2, 2, 27, 1, 64),
-               ((1, 1, 1), 0.0, 7, 19, 0, 64), ((5, 6, 7), 1.0, 7, 19, 0, 64)]
+               ((1, 1, 1), 0.0, 7, 19, 0, 64), ((5, 6, 7), 1.0, 7, 19, 0, 64),
+               ((21, 35, 19), 0.35, 7, 19, 2, 64), ((7, 9, 40), 0.3, 4, 27, 2, 1),
+               ((1, 1, 1), 0.0, 7, 27, 2, 64)]
 
 
 @pytest.mark.parametrize("shape,solid,periodic,q,order,align", BUILD_CASES)

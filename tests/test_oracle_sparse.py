@@ -24,6 +24,13 @@ def brute_force_tables(lab, periodic, q, order, align):
     def key(p):
         if order == 1:
             return p[0] + nx * (p[1] + ny * p[2])
+        if order == 2:
+            ty, tz = p[1] // 8, p[2] // 8
+            t = 0
+            for b in range(8):
+                t |= ((ty >> b) & 1) << (2 * b)
+                t |= ((tz >> b) & 1) << (2 * b + 1)
+            return (t, p[2] % 8, p[1] % 8, p[0])
         k = 0
         for b in range(10):
             for a in range(3):
@@ -60,7 +67,8 @@ def brute_force_tables(lab, periodic, q, order, align):
 
 CASES = [((5, 4, 3), 0.3, 7, 19, 0, 1), ((6, 6, 6), 0.5, 0, 19, 0, 64),
          ((4, 7, 5), 0.2, 5, 27, 0, 8), ((8, 3, 5), 0.4, 3, 27, 1, 1),
-         ((3, 3, 3), 0.0, 7, 19, 1, 4), ((7, 5, 6), 0.6, 2, 19, 0, 16)]
+         ((3, 3, 3), 0.0, 7, 19, 1, 4), ((7, 5, 6), 0.6, 2, 19, 0, 16),
+         ((9, 19, 17), 0.3, 7, 19, 2, 64), ((5, 20, 9), 0.4, 3, 27, 2, 1)]
 
 
 @pytest.mark.parametrize("shape,solid,periodic,q,order,align", CASES)
