@@ -105,7 +105,9 @@ def main():
     ap.add_argument("--L", type=int, default=256)
     ap.add_argument("--tau", type=float, default=0.8)
     ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16dev", "bf16dev", "f32dev"])
-    ap.add_argument("--order", default="morton", choices=["morton", "lex"])
+    ap.add_argument("--order", default="blocked", choices=["morton", "lex", "blocked"])
+    ap.add_argument("--index", default="16", choices=["16", "32"],
+                    help="index-list form: 16 = compact (2 B/entry), 32 = int32")
     ap.add_argument("--dense-steps", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -125,7 +127,8 @@ def main():
     storage = {"f64": lbm.STORE_F64, "f32": lbm.STORE_F32, "f16dev": lbm.STORE_F16DEV,
                "bf16dev": lbm.STORE_BF16DEV, "f32dev": lbm.STORE_F32DEV}[args.storage]
     dev_exp = 14 if storage == lbm.STORE_F16DEV else 0
-    order = lbm.ORDER_MORTON if args.order == "morton" else lbm.ORDER_LEX
+    order = {"morton": lbm.ORDER_MORTON, "lex": lbm.ORDER_LEX,
+             "blocked": lbm.ORDER_BLOCKED}[args.order]
     q, magic, force = 19, 3.0 / 16.0, (1e-6, 0.0, 0.0)
     torch.cuda.set_device(0)
 
@@ -137,6 +140,12 @@ def main():
     torch.cuda.synchronize()
     tb = time.perf_counter()
     dom = lbm.SparseDomain(lab_dev, per, q, order, 64)
+    index_form = "int32"
+    escaped = None
+    if args.index == "16":
+        escaped = dom.compact()
+        index_form = "compact16"
+        log(f"compact index-list: {100 * escaped:.2f}% of entries escape to int32")
     torch.cuda.synchronize()
     build_ms = (time.perf_counter() - tb) * 1e3
     nf = dom.n_fluid
@@ -166,7 +175,14 @@ def main():
     t_even = sum(even_d) / max(len(even_d), 1)
     mflups = nf * K / wall / 1e6
     b_pdf = lbm.STORE_BYTES[storage]
-    b_odd, b_even, b_alg = bytes_per_flup(q, b_pdf)
+    b_idx = 2 if index_form == "compact16" else 4
+    b_odd, b_even, b_alg = bytes_per_flup(q, b_pdf, b_idx)
+    if index_form == "compact16":
+        # one int32 base per direction per 256 cells; escaped entries also
+        # read their int32 position
+        b_odd += (q - 1) * 4 / 256 + (q - 1) * 4 * escaped
+        b_alg = 0.5 * (b_odd + b_even)
+    b_alg_int32 = bytes_per_flup(q, b_pdf, 4)[2]
     log(f"timed {K} steps: {wall * 1e3:.2f} ms, {mflups:.0f} MFLUPS; odd {t_odd * 1e6:.1f} us, "
         f"even {t_even * 1e6:.1f} us")
     red = sol.reduce(coll)
@@ -221,9 +237,13 @@ def main():
         "config": {"workload": f"sparse D3Q19 TRT AA, {args.L}^3 periodic overlapping-sphere "
                                f"packing phi={info['phi']:.3f} (r 4-12, seed {info['seed']})",
                    "n_fluid": nf, "tau": args.tau, "magic": magic, "force": list(force),
-                   "storage": args.storage, "order": args.order, "stride": dom.stride},
+                   "storage": args.storage, "order": args.order, "index": index_form,
+                   "index_escaped_fraction": escaped,
+                   "stride": dom.stride},
         "pct_hbm_peak": round(100.0 * mflups * 1e6 * b_alg / (HBM_PEAK_GBS * 1e9), 2),
         "bytes_per_flup_alg": b_alg,
+        "pct_hbm_peak_int32_index_model": round(
+            100.0 * mflups * 1e6 * b_alg_int32 / (HBM_PEAK_GBS * 1e9), 2),
         "roofline": {"bound": "hbm", "kernel": "AA odd step (index gather + collide + scatter)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,

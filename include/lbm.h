@@ -142,6 +142,9 @@ typedef struct {
   int32_t dev_exp;       /* 16-bit formats: stored = (f - w) * 2^dev_exp, 0..24 */
   void* pdf;             /* device, q*stride elements of the storage type      */
   const int32_t* index;  /* device, (q-1)*stride (from lbm_build_sparse)       */
+  const void* index16;   /* device, compact index-list (lbm_compress_index) of  */
+                         /* the same index, or NULL; when set, index reads use  */
+                         /* it and fall back to `index` for escaped entries     */
   const int32_t* links;  /* device, 2*n_links or NULL when n_links == 0        */
   int64_t t;             /* steps taken. t even: populations in natural slots  */
 } lbm_state;
@@ -178,6 +181,24 @@ typedef struct {
   int32_t reserved;
   lbm_bclass cls[8];
 } lbm_bspec;
+
+/* Compact index-list.  The list positions are cut into tiles of 256
+ * cells; for tile t and direction i the library stores one int32 base b,
+ * and per cell a uint16 o: 0xFFFF = upstream cell not fluid (position
+ * opp(i)*S + k), 0xFFFE = escaped (position read from the int32
+ * index-list), else position i*S + k + b + o.  b is chosen per tile and
+ * direction so that as many entries as possible fit the 16-bit window.
+ * Buffer: uint16 o[(q-1)][S]; then (256-byte aligned) int32 b[tiles][q-1];
+ * then (aligned) uint32 per-tile escape counts and their total.
+ * Halves the index bytes read by each odd step.
+ *  lbm_index16_bytes: device bytes of the compact form (host only).
+ *  lbm_compress_index: index device int32[(q-1)*S] from lbm_build_sparse;
+ *      index16 device buffer of lbm_index16_bytes(layout); n_escaped host
+ *      (may be NULL) receives the number of escaped entries.  SYNC.
+ *      lbm_state.index stays required next to index16. */
+uint64_t lbm_index16_bytes(const lbm_layout* layout);
+lbm_status lbm_compress_index(const lbm_layout* layout, const int32_t* index, void* index16,
+                              uint64_t* n_escaped, void* stream);
 
 /* Initialise every fluid cell to the equilibrium of (rho0, u0) and set
  * state->t = 0.  u0: host double[3].  Padding slots are zeroed (deviation)

@@ -123,6 +123,37 @@ void coll_rates(const lbm_collision* c, double& om1, double& om2) {
   }
 }
 
+// Sub-buffers of a compact index-list of `layout` starting at `p`.
+struct Index16View {
+  uint16_t* off;
+  int32_t* base;
+  uint32_t* flags;
+  uint32_t ntiles;
+  uint64_t bytes;
+};
+
+uint64_t align256(uint64_t v) { return (v + 255) & ~(uint64_t)255; }
+
+Index16View index16_view(const lbm_layout& L, const void* p) {
+  Index16View v;
+  const uint64_t S = (uint64_t)L.stride, qm = (uint64_t)(L.q - 1);
+  v.ntiles = (uint32_t)((S + kTile16 - 1) / kTile16);
+  const uint64_t off_b = align256(2 * qm * S);
+  const uint64_t base_b = align256(4 * qm * v.ntiles);
+  const uint64_t flag_b = align256(4 * ((uint64_t)v.ntiles + 1));
+  v.bytes = off_b + base_b + flag_b;
+  v.off = nullptr;
+  v.base = nullptr;
+  v.flags = nullptr;
+  if (p) {
+    char* c = (char*)p;
+    v.off = (uint16_t*)c;
+    v.base = (int32_t*)(c + off_b);
+    v.flags = (uint32_t*)(c + off_b + base_b);
+  }
+  return v;
+}
+
 Seg make_seg(const lbm_state* s, const lbm_collision* c) {
   Seg g;
   memset(&g, 0, sizeof(g));
@@ -130,6 +161,12 @@ Seg make_seg(const lbm_state* s, const lbm_collision* c) {
   g.idx = s->index;
   g.S = (uint32_t)s->layout.stride;
   g.nf = (uint32_t)s->layout.n_fluid;
+  if (s->index16) {
+    Index16View v = index16_view(s->layout, s->index16);
+    g.off16 = v.off;
+    g.base16 = v.base;
+    g.ntiles16 = v.ntiles;
+  }
   if (c) {
     coll_rates(c, g.om1, g.om2);
     for (int a = 0; a < 3; ++a) g.F[a] = c->force[a];
@@ -166,13 +203,11 @@ lbm_status link_update(const lbm_state* s, const lbm_bspec* bs, hipStream_t st) 
   return LBM_OK;
 }
 
-hipError_t launch_aa(int q, int coll, int storage, bool odd, const StepArgs& a, int block,
-                     hipStream_t st) {
-  if (q == 19) return launch_aa_q19(coll, storage, odd, a, block, st);
-  return launch_aa_q27(coll, storage, odd, a, block, st);
+hipError_t launch_aa(int q, int coll, int storage, bool odd, bool idx16, const StepArgs& a,
+                     int block, hipStream_t st) {
+  if (q == 19) return launch_aa_q19(coll, storage, odd, idx16, a, block, st);
+  return launch_aa_q27(coll, storage, odd, idx16, a, block, st);
 }
-
-uint64_t align256(uint64_t v) { return (v + 255) & ~(uint64_t)255; }
 
 uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
@@ -293,6 +328,29 @@ lbm_status lbm_build_sparse(const uint8_t* labels, int32_t nx, int32_t ny, int32
   return LBM_OK;
 }
 
+// ------------------------------------------------ compact index-list
+uint64_t lbm_index16_bytes(const lbm_layout* L) {
+  if (!L || (L->q != 19 && L->q != 27) || L->stride < 0) return 0;
+  return index16_view(*L, nullptr).bytes;
+}
+
+lbm_status lbm_compress_index(const lbm_layout* L, const int32_t* index, void* index16,
+                              uint64_t* n_escaped, void* stream) {
+  if (!L || !index || !index16) return fail(LBM_EINVAL, "layout/index/index16 is NULL");
+  lbm_status rc = check_layout(*L);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  Index16View v = index16_view(*L, index16);
+  HIP_TRY(launch_compress_index(L->q, index, (uint32_t)L->stride, (uint32_t)L->n_fluid, v.ntiles,
+                                v.off, v.base, v.flags, st),
+          "compress index");
+  uint32_t esc = 0;
+  HIP_TRY(hipMemcpyAsync(&esc, v.flags + v.ntiles, 4, hipMemcpyDeviceToHost, st), "index16 count");
+  HIP_TRY(hipStreamSynchronize(st), "index16 sync");
+  if (n_escaped) *n_escaped = esc;
+  return LBM_OK;
+}
+
 // ---------------------------------------------------------- stepping
 lbm_status lbm_init_equilibrium(lbm_state* s, double rho0, const double* u0, void* stream) {
   lbm_status rc = check_state(s);
@@ -320,22 +378,30 @@ static lbm_status step_group(lbm_state* const* states, const lbm_collision* cons
       lbm_status rc = link_update(states[j], bspecs ? bspecs[j] : nullptr, st);
       if (rc) return rc;
     }
-    for (int32_t j0 = 0; j0 < n; j0 += kMaxSeg) {
-      StepArgs a;
-      memset(&a, 0, sizeof(a));
-      a.xcd_remap = cfg.xcd_remap;
-      uint32_t tiles = 0;
-      int ns = 0;
-      for (int32_t j = j0; j < n && j < j0 + kMaxSeg; ++j) {
-        if (states[j]->layout.n_fluid == 0) continue;
-        Seg g = make_seg(states[j], colls[j]);
-        g.tile0 = tiles;
-        tiles += ceil_div(g.nf, (uint64_t)cfg.block);
-        a.seg[ns++] = g;
+    // Odd steps of states with a compact index-list run in launches of
+    // their own (a different kernel); even steps never read indices.
+    for (int form = 0; form < 2; ++form) {
+      const bool idx16 = odd && form == 1;
+      int32_t j = 0;
+      while (j < n) {
+        StepArgs a;
+        memset(&a, 0, sizeof(a));
+        a.xcd_remap = cfg.xcd_remap;
+        uint32_t tiles = 0;
+        int ns = 0;
+        for (; j < n && ns < kMaxSeg; ++j) {
+          const bool has16 = odd && states[j]->index16 != nullptr;
+          if (states[j]->layout.n_fluid == 0 || has16 != idx16) continue;
+          Seg g = make_seg(states[j], colls[j]);
+          g.tile0 = tiles;
+          tiles += ceil_div(g.nf, (uint64_t)cfg.block);
+          a.seg[ns++] = g;
+        }
+        a.nseg = ns;
+        a.ntiles = tiles;
+        if (ns > 0) HIP_TRY(launch_aa(q, kind, storage, odd, idx16, a, cfg.block, st), "AA step");
       }
-      a.nseg = ns;
-      a.ntiles = tiles;
-      if (ns > 0) HIP_TRY(launch_aa(q, kind, storage, odd, a, cfg.block, st), "AA step");
+      if (!odd) break;
     }
     for (int32_t j = 0; j < n; ++j) states[j]->t += 1;
   }

@@ -147,11 +147,13 @@ __device__ __forceinline__ void gather_post(const Seg& g, uint32_t k,
   using R = typename SP::R;
   const T* pdf = static_cast<const T*>(g.pdf);
   const R isc = R(g.inv_scale);
+  const uint32_t t16 = k / kTile16;
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
     uint32_t pos;
     if (ODD_T && j > 0)
-      pos = (uint32_t)g.idx[(size_t)(opp(j) - 1) * g.S + k];
+      pos = g.off16 ? pos16(g, Q, opp(j), j, k, t16)
+                    : (uint32_t)g.idx[(size_t)(opp(j) - 1) * g.S + k];
     else
       pos = (uint32_t)j * g.S + k;
     d[j] = SP::load(pdf[pos], R(Lattice<Q>::w(j)), isc);

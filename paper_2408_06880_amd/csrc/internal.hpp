@@ -10,10 +10,10 @@
 namespace lbm {
 
 // AA step kernels (step_q19.hip, step_q27.hip)
-hipError_t launch_aa_q19(int coll, int storage, bool odd, const StepArgs& a, int block,
-                         hipStream_t st);
-hipError_t launch_aa_q27(int coll, int storage, bool odd, const StepArgs& a, int block,
-                         hipStream_t st);
+hipError_t launch_aa_q19(int coll, int storage, bool odd, bool idx16, const StepArgs& a,
+                         int block, hipStream_t st);
+hipError_t launch_aa_q27(int coll, int storage, bool odd, bool idx16, const StepArgs& a,
+                         int block, hipStream_t st);
 
 // Boundary-class coefficients of one solve, precomputed on the host:
 // for class c, type[c] in {0 noslip, 1 UBB, 2 pressure}; u[c][3]; rho[c].
@@ -66,6 +66,12 @@ hipError_t launch_build_emit(const BuildArgs& b, const uint32_t* counts, uint32_
                              int32_t* links, hipStream_t st);
 hipError_t launch_build_index(const BuildArgs& b, const int32_t* cells, const int32_t* inv,
                               uint32_t S, uint32_t n_fluid, int32_t* index, hipStream_t st);
+
+// index16.hip: compact index-list from the int32 one; flags gets one word
+// per tile plus the OR of all of them at [ntiles].
+hipError_t launch_compress_index(int q, const int32_t* index, uint32_t S, uint32_t nf,
+                                 uint32_t ntiles, uint16_t* off, int32_t* base, uint32_t* flags,
+                                 hipStream_t st);
 
 // dense.hip
 struct DenseArgs {

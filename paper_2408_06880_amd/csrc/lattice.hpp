@@ -110,13 +110,21 @@ struct Store<ST_BF16DEV> {
 // ---------------------------------------------------------------------------
 constexpr int kMaxSeg = 16;
 
+// Compact index-list: tiles of kTile16 list positions.
+constexpr uint32_t kTile16 = 256;
+constexpr uint16_t kBounce16 = 0xFFFFu;  // upstream cell not fluid
+constexpr uint16_t kEscape16 = 0xFFFEu;  // read the int32 index-list
+constexpr uint32_t kMaxOff16 = 0xFFFDu;  // largest stored offset
+
 struct Seg {
-  void* pdf;             // PDF-list of this solve
-  const int32_t* idx;    // index-list (odd steps)
-  uint32_t S;            // stride
-  uint32_t nf;           // fluid cells
-  uint32_t tile0;        // first tile of this segment in the launch
-  uint32_t pad;
+  void* pdf;               // PDF-list of this solve
+  const int32_t* idx;      // index-list (odd steps), or null when off16 is set
+  const uint16_t* off16;   // compact index-list offsets, or null
+  const int32_t* base16;   // compact index-list tile bases
+  uint32_t ntiles16;       // tiles of the compact index-list
+  uint32_t S;              // stride
+  uint32_t nf;             // fluid cells
+  uint32_t tile0;          // first tile of this segment in the launch
   double om1;            // SRT omega / TRT omega+ / cumulant shear rate
   double om2;            // TRT omega- / cumulant bulk rate
   double F[3];           // body force
@@ -131,6 +139,17 @@ struct StepArgs {
   int32_t pad;
   Seg seg[kMaxSeg];
 };
+
+// Pull position of population i of cell k from the compact index-list
+// (t16 = the cell's compact tile; tile bases are stored [tile][direction]).
+__device__ __forceinline__ uint32_t pos16(const Seg& g, int q, int i, int oi, uint32_t k,
+                                          uint32_t t16) {
+  const uint16_t o = g.off16[(size_t)(i - 1) * g.S + k];
+  const int32_t b = g.base16[(size_t)t16 * (q - 1) + (i - 1)];
+  if (o >= kEscape16)
+    return o == kBounce16 ? (uint32_t)oi * g.S + k : (uint32_t)g.idx[(size_t)(i - 1) * g.S + k];
+  return (uint32_t)((int32_t)((uint32_t)i * g.S + k) + b + (int32_t)o);
+}
 
 // XCD-aware tile order.  Workgroups are dispatched round-robin over the 8
 // XCDs (workgroup v runs on XCD v % 8); mapping the workgroups of one XCD to

@@ -12,9 +12,9 @@
 //   reads, fully coalesced.
 //
 // One thread updates one fluid cell; a workgroup covers BLOCK consecutive
-// cells of one segment (solve).  Consecutive cells are consecutive along the
-// Morton curve, so the gathers of a wavefront stay within a few cache lines
-// per direction.
+// cells of one segment (solve).  Consecutive list positions are neighbours
+// along the list order (blocked, lexicographic or Morton), so the gathers of
+// a wavefront stay within a few cache lines per direction.
 #pragma once
 
 #include "cumulant.hpp"
@@ -44,14 +44,14 @@ __device__ __forceinline__ CollParams<R> seg_params(const Seg& g) {
   return p;
 }
 
-template <int Q, int COLL, int ST, bool ODD>
+template <int Q, int COLL, int ST, bool ODD, bool IDX16>
 __global__ __launch_bounds__(256) void k_aa_step(const StepArgs a) {
   using SP = Store<ST>;
   using T = typename SP::T;
   using R = typename SP::R;
   const uint32_t tile = a.xcd_remap ? xcd_tile(blockIdx.x, a.ntiles) : blockIdx.x;
   const int s = seg_of(a, tile);
-  const Seg& g = a.seg[s];
+  const Seg g = a.seg[s];
   const uint32_t k = (tile - g.tile0) * blockDim.x + threadIdx.x;
   if (k >= g.nf) return;
   T* __restrict__ pdf = static_cast<T*>(g.pdf);
@@ -59,12 +59,42 @@ __global__ __launch_bounds__(256) void k_aa_step(const StepArgs a) {
   const R sc = R(g.scale), isc = R(g.inv_scale);
   R d[Q];
   if constexpr (ODD) {
-    const int32_t* __restrict__ idx = g.idx;
     uint32_t pos[Q];
     pos[0] = k;
+    if constexpr (IDX16) {
+      // All offset loads first, then the tile's bases (the workgroup lies in
+      // one compact tile: the block size divides kTile16), then branch-free
+      // positions; escaped entries are patched under a wave-uniform branch.
+      const uint16_t* __restrict__ off = g.off16;
+      const uint32_t t16 = ((tile - g.tile0) * blockDim.x) / kTile16;
+      const int32_t* __restrict__ base = g.base16 + (size_t)t16 * (Q - 1);
+      uint32_t o[Q];
+      int32_t b[Q];
 #pragma unroll
-    for (int i = 1; i < Q; ++i)
-      pos[i] = static_cast<uint32_t>(__builtin_nontemporal_load(idx + (size_t)(i - 1) * S + k));
+      for (int i = 1; i < Q; ++i) o[i] = __builtin_nontemporal_load(off + (size_t)(i - 1) * S + k);
+#pragma unroll
+      for (int i = 1; i < Q; ++i) b[i] = base[i - 1];
+      bool esc = false;
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        const uint32_t fl = (uint32_t)((int32_t)((uint32_t)i * S + k) + b[i] + (int32_t)o[i]);
+        const uint32_t bb = (uint32_t)opp(i) * S + k;
+        const uint32_t m = 0u - (uint32_t)(o[i] == kBounce16);  // all ones: bounce-back
+        pos[i] = (fl & ~m) | (bb & m);
+        esc = esc || o[i] == kEscape16;
+      }
+      if (__ballot(esc)) {
+        const int32_t* __restrict__ idx = g.idx;
+#pragma unroll
+        for (int i = 1; i < Q; ++i)
+          if (o[i] == kEscape16) pos[i] = (uint32_t)idx[(size_t)(i - 1) * S + k];
+      }
+    } else {
+      const int32_t* __restrict__ idx = g.idx;
+#pragma unroll
+      for (int i = 1; i < Q; ++i)
+        pos[i] = static_cast<uint32_t>(__builtin_nontemporal_load(idx + (size_t)(i - 1) * S + k));
+    }
 #pragma unroll
     for (int i = 0; i < Q; ++i) d[i] = SP::load(pdf[pos[i]], R(Lattice<Q>::w(i)), isc);
     collide<Q, COLL, R>(d, seg_params<R>(g));
@@ -85,24 +115,27 @@ __global__ __launch_bounds__(256) void k_aa_step(const StepArgs a) {
 
 // Host-side dispatch over (collision, storage, parity) for one Q.
 template <int Q, int COLL, int ST>
-inline hipError_t launch_aa_cs(bool odd, const StepArgs& a, int block, hipStream_t st) {
+inline hipError_t launch_aa_cs(bool odd, bool idx16, const StepArgs& a, int block,
+                               hipStream_t st) {
   dim3 grid(a.ntiles), blk(block);
-  if (odd)
-    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, true>), grid, blk, 0, st, a);
+  if (odd && idx16)
+    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, true, true>), grid, blk, 0, st, a);
+  else if (odd)
+    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, true, false>), grid, blk, 0, st, a);
   else
-    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, false>), grid, blk, 0, st, a);
+    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, false, false>), grid, blk, 0, st, a);
   return hipGetLastError();
 }
 
 template <int Q, int COLL>
-inline hipError_t launch_aa_c(int storage, bool odd, const StepArgs& a, int block,
+inline hipError_t launch_aa_c(int storage, bool odd, bool idx16, const StepArgs& a, int block,
                               hipStream_t st) {
   switch (storage) {
-    case ST_F64: return launch_aa_cs<Q, COLL, ST_F64>(odd, a, block, st);
-    case ST_F32: return launch_aa_cs<Q, COLL, ST_F32>(odd, a, block, st);
-    case ST_F16DEV: return launch_aa_cs<Q, COLL, ST_F16DEV>(odd, a, block, st);
-    case ST_BF16DEV: return launch_aa_cs<Q, COLL, ST_BF16DEV>(odd, a, block, st);
-    case ST_F32DEV: return launch_aa_cs<Q, COLL, ST_F32DEV>(odd, a, block, st);
+    case ST_F64: return launch_aa_cs<Q, COLL, ST_F64>(odd, idx16, a, block, st);
+    case ST_F32: return launch_aa_cs<Q, COLL, ST_F32>(odd, idx16, a, block, st);
+    case ST_F16DEV: return launch_aa_cs<Q, COLL, ST_F16DEV>(odd, idx16, a, block, st);
+    case ST_BF16DEV: return launch_aa_cs<Q, COLL, ST_BF16DEV>(odd, idx16, a, block, st);
+    case ST_F32DEV: return launch_aa_cs<Q, COLL, ST_F32DEV>(odd, idx16, a, block, st);
   }
   return hipErrorInvalidValue;
 }

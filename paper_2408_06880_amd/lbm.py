@@ -46,7 +46,7 @@ class lbm_layout(ctypes.Structure):
 
 class lbm_state(ctypes.Structure):
     _fields_ = [("layout", lbm_layout), ("storage", _i32), ("dev_exp", _i32), ("pdf", _vp),
-                ("index", _vp), ("links", _vp), ("t", _i64)]
+                ("index", _vp), ("index16", _vp), ("links", _vp), ("t", _i64)]
 
 
 class lbm_collision(ctypes.Structure):
@@ -93,6 +93,9 @@ _SIGS = {
     "lbm_build_workspace_bytes": (_u64, [_i32, _i32, _i32, _i32]),
     "lbm_build_sparse": (_i32, [_vp, _i32, _i32, _i32, _u32, _i32, _i32, _i32, _vp,
                                 ctypes.POINTER(lbm_layout), _vp, _vp, _vp, _vp]),
+    "lbm_index16_bytes": (_u64, [ctypes.POINTER(lbm_layout)]),
+    "lbm_compress_index": (_i32, [ctypes.POINTER(lbm_layout), _vp, _vp,
+                                  ctypes.POINTER(_u64), _vp]),
     "lbm_init_equilibrium": (_i32, [ctypes.POINTER(lbm_state), _f64, ctypes.POINTER(_f64), _vp]),
     "lbm_step": (_i32, [ctypes.POINTER(lbm_state), _i32, ctypes.POINTER(lbm_collision),
                         ctypes.POINTER(lbm_bspec), _vp]),
@@ -182,6 +185,18 @@ def lbm_build_sparse(labels, nx, ny, nz, periodic, q, order, align, workspace, l
           _ptr(workspace), ctypes.byref(lay), _ptr(cells), _ptr(index), _ptr(links),
           _stream(stream))
     return lay
+
+
+def lbm_index16_bytes(layout):
+    return int(load().lbm_index16_bytes(ctypes.byref(layout)))
+
+
+def lbm_compress_index(layout, index, index16, stream=None):
+    """Returns the number of escaped entries."""
+    n = _u64(0)
+    _call("lbm_compress_index", ctypes.byref(layout), _ptr(index), _ptr(index16),
+          ctypes.byref(n), _stream(stream))
+    return int(n.value)
 
 
 def lbm_init_equilibrium(state, rho0=1.0, u0=(0.0, 0.0, 0.0), stream=None):
@@ -316,7 +331,19 @@ class SparseDomain:
         self.shape = (nz, ny, nx)
         self.q = q
         self.periodic = periodic
+        self.index16 = None
         del ws
+
+    def compact(self, stream=None):
+        """Build the compact (16-bit) index-list next to the int32 one;
+        returns the fraction of entries that escape to the int32 form."""
+        import torch
+        buf = torch.empty(max(lbm_index16_bytes(self.layout), 1), dtype=torch.uint8,
+                          device=self.index.device)
+        n_esc = lbm_compress_index(self.layout, self.index, buf, stream)
+        self.index16 = buf
+        self.escaped = n_esc
+        return n_esc / max((self.q - 1) * self.n_fluid, 1)
 
     @property
     def n_fluid(self):
@@ -345,6 +372,7 @@ class Solver:
         st.dev_exp = dev_exp
         st.pdf = self.pdf.data_ptr()
         st.index = domain.index.data_ptr()
+        st.index16 = domain.index16.data_ptr() if domain.index16 is not None else None
         st.links = domain.links.data_ptr() if domain.n_links else None
         st.t = 0
         self.state = st

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(lbm.lbm_layout) == 56
-    assert ctypes.sizeof(lbm.lbm_state) == 56 + 8 + 24 + 8
+    assert ctypes.sizeof(lbm.lbm_state) == 56 + 8 + 32 + 8
     assert ctypes.sizeof(lbm.lbm_collision) == 8 + 8 * 6
     assert ctypes.sizeof(lbm.lbm_bspec) == 8 + 8 * 40
     assert ctypes.sizeof(lbm.lbm_reduction) == 48
@@ -47,6 +47,8 @@ def test_workspace_queries():
     lay = lbm.lbm_layout()
     lay.n_fluid = 1000
     assert lbm.lbm_reduce_workspace_bytes(lay) >= 4 * 5 * 8
+    lay.q, lay.stride = 19, 1024
+    assert lbm.lbm_index16_bytes(lay) >= 18 * 1024 * 2 + 18 * 4 * 4
 
 
 def _fake_state(q=19, nf=100, S=128, storage=lbm.STORE_F32):
@@ -97,3 +99,15 @@ def test_launch_table_roundtrip():
     lbm.lbm_set_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F16DEV, 128, 0)
     assert lbm.lbm_get_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F16DEV) == (128, 0)
     lbm.lbm_set_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F16DEV, *old)
+
+
+def test_header_compiles_as_c_and_cxx(tmp_path):
+    """include/lbm.h is self-contained C and C++ (no HIP types)."""
+    import subprocess
+    src = tmp_path / "use.c"
+    src.write_text('#include "lbm.h"\nint main(void) { lbm_state s; (void)s; return 0; }\n')
+    inc = os.path.join(ROOT, "include")
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-fsyntax-only", f"-I{inc}", str(src)],
+                   check=True)
+    subprocess.run(["g++", "-std=c++11", "-Wall", "-Werror", "-fsyntax-only", "-x", "c++",
+                    f"-I{inc}", str(src)], check=True)

@@ -429,3 +429,89 @@ def test_empty_and_single_cell_domains():
     sol.step(4, lbm.collision(lbm.COLL_SRT, tau=0.9, force=(1e-3, 0, 0)))
     r = sol.reduce(lbm.collision(lbm.COLL_SRT, tau=0.9, force=(1e-3, 0, 0)))
     assert abs(r.mass - 1.0) < 1e-15
+
+
+# -------------------------------------------------- compact index-list
+def _decode_index16(dom):
+    """Host decode of the compact index-list (layout documented in lbm.h);
+    escaped entries are read from the int32 list."""
+    q, S, nf = dom.q, dom.stride, dom.n_fluid
+    raw = dom.index16.cpu().numpy()
+    idx32 = dom.index[:(q - 1) * S].cpu().numpy().reshape(q - 1, S).astype(np.int64)
+    a256 = lambda v: (v + 255) // 256 * 256
+    ntiles = (S + 255) // 256
+    off = raw[:2 * (q - 1) * S].view(np.uint16).reshape(q - 1, S).astype(np.int64)
+    b0 = a256(2 * (q - 1) * S)
+    base = raw[b0:b0 + 4 * (q - 1) * ntiles].view(np.int32).reshape(ntiles, q - 1).T.astype(
+        np.int64)
+    _, _, opp = oracle.stencil(q)
+    k = np.arange(nf)
+    out = np.empty((q - 1, nf), np.int64)
+    n_esc = 0
+    for i in range(1, q):
+        o = off[i - 1, :nf]
+        fl = i * S + k + base[i - 1, k // 256] + o
+        out[i - 1] = np.where(o == 0xFFFF, opp[i] * S + k,
+                              np.where(o == 0xFFFE, idx32[i - 1, :nf], fl))
+        n_esc += int(np.count_nonzero(o == 0xFFFE))
+        # entries stored as offsets lie in the fluid block of direction i
+        assert np.all((fl[o < 0xFFFE] >= i * S) & (fl[o < 0xFFFE] < (i + 1) * S))
+    return out, n_esc
+
+
+@pytest.mark.parametrize("order", [lbm.ORDER_BLOCKED, lbm.ORDER_LEX, lbm.ORDER_MORTON])
+@pytest.mark.parametrize("q", [19, 27])
+def test_index16_decodes_to_int32_table(order, q):
+    lab = inputs.random_mask((40, 33, 29), 0.35, seed=q + order, n_classes=2, class_fraction=0.3)
+    dom = lbm.SparseDomain(lab, 5, q, order)
+    dom.compact()
+    torch.cuda.synchronize()
+    S, nf = dom.stride, dom.n_fluid
+    ref = dom.index[:(q - 1) * S].cpu().numpy().reshape(q - 1, S)[:, :nf].astype(np.int64)
+    got, n_esc = _decode_index16(dom)
+    assert np.array_equal(got, ref)
+    assert n_esc == dom.escaped
+
+
+def test_index16_steps_bitwise_equal_to_int32():
+    """The compact index-list changes how positions are stored, not which:
+    PDFs, moments and reductions are bitwise those of the int32 path."""
+    lab = inputs.random_mask((30, 28, 26), 0.3, seed=4, n_classes=3, class_fraction=0.5)
+    coll, bs, _ = _params(27, lbm.COLL_CUMULANT, 0.7, (1e-5, 0, 0), CLASSES)
+    d32 = lbm.SparseDomain(lab, 3, 27, lbm.ORDER_BLOCKED)
+    d16 = lbm.SparseDomain(lab, 3, 27, lbm.ORDER_BLOCKED)
+    d16.compact()
+    torch.cuda.synchronize()
+    a = lbm.Solver(d32, lbm.STORE_F32)
+    b = lbm.Solver(d16, lbm.STORE_F32)
+    f0 = _random_state(27, d32.n_fluid, seed=3)
+    _upload(a, f0, 0)
+    _upload(b, f0, 0)
+    a.step(11, coll, bs)
+    b.step(11, coll, bs)
+    torch.cuda.synchronize()
+    assert torch.equal(a.pdf, b.pdf)
+    nf = d32.n_fluid
+    ra, ua = a.moments(coll)
+    rb, ub = b.moments(coll)
+    assert torch.equal(ra[:nf], rb[:nf]) and torch.equal(ua[:, :nf], ub[:, :nf])
+    xa, xb = a.reduce(coll), b.reduce(coll)
+    assert (xa.mass, tuple(xa.mom)) == (xb.mass, tuple(xb.mom))
+
+
+@pytest.mark.parametrize("order", [2, 1])
+def test_index16_full_size_packing(packing256, order):
+    """The benchmark geometry: the compact list decodes to the oracle's
+    int32 index-list, with escapes only where a tile's offsets form two
+    clusters (block borders, the periodic wrap)."""
+    lab, per, info, _ = packing256
+    ref = oracle.sparse_build(lab, per, 19, order=order, align=64)
+    dom = lbm.SparseDomain(lab, per, 19, order)
+    frac = dom.compact()
+    torch.cuda.synchronize()
+    _say("escaped fraction", order, frac)
+    nf, S = ref.n_fluid, ref.stride
+    assert dom.n_fluid == nf and dom.stride == S
+    got, n_esc = _decode_index16(dom)
+    assert np.array_equal(got, ref.index.reshape(18, S)[:, :nf])
+    assert frac < 0.2
