@@ -96,6 +96,25 @@ def cpu_baseline(lab, per, q, tau, magic, force, n_fluid, budget_s):
                       f"({n_fluid} fluid cells) after one untimed step, {el:.1f} s"}
 
 
+def recorded_traffic(workload_key):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summaries in profiles/, if one matches this workload
+    and was taken on the current kernel sources; else None."""
+    import glob
+
+    from paper_2408_06880_amd import kernel_source_hash
+    h = kernel_source_hash()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        kv = {}
+        for line in open(path):
+            if line.startswith("traffic_") and ":" in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        if kv.get("traffic_workload") == workload_key and kv.get("traffic_source_hash") == h:
+            return float(kv["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
+    return None, None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,6 +239,10 @@ def main():
         log(f"cpu oracle {cpu['value']:.1f} MFLUPS on {cpu['cores']} threads")
 
     achieved = nf * b_odd / t_odd / 1e9
+    workload = (f"sparse D3Q19 TRT AA, {args.L}^3 periodic overlapping-sphere packing "
+                f"phi={info['phi']:.3f} (r 4-12, seed {info['seed']})")
+    traffic, traffic_src = recorded_traffic(
+        f"{workload}; storage={args.storage}; order={args.order}; index={index_form}")
     out = {
         "metric": METRIC,
         "value": round(mflups, 1),
@@ -234,8 +257,7 @@ def main():
         "dtype": {"f64": "f64", "f32": "f32", "f16dev": "f32 (f16 storage)",
                   "bf16dev": "f32 (bf16 storage)", "f32dev": "f32"}[args.storage],
         "data": "synthetic",
-        "config": {"workload": f"sparse D3Q19 TRT AA, {args.L}^3 periodic overlapping-sphere "
-                               f"packing phi={info['phi']:.3f} (r 4-12, seed {info['seed']})",
+        "config": {"workload": workload,
                    "n_fluid": nf, "tau": args.tau, "magic": magic, "force": list(force),
                    "storage": args.storage, "order": args.order, "index": index_form,
                    "index_escaped_fraction": escaped,
@@ -246,7 +268,8 @@ def main():
             100.0 * mflups * 1e6 * b_alg_int32 / (HBM_PEAK_GBS * 1e9), 2),
         "roofline": {"bound": "hbm", "kernel": "AA odd step (index gather + collide + scatter)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_source": traffic_src,
                      "bytes_per_launch": nf * b_odd, "avg_launch_us": round(t_odd * 1e6, 2)},
         "even_kernel": {"achieved_gbs": round(nf * b_even / t_even / 1e9, 1),
                         "avg_launch_us": round(t_even * 1e6, 2), "bytes_per_launch": nf * b_even},

@@ -11,3 +11,17 @@ Submodules are imported lazily so that the input generators can be used on a
 host without a GPU.
 """
 __all__ = ["lbm", "inputs", "build", "server", "autotune"]
+
+
+def kernel_source_hash() -> str:
+    """Short hash of the HIP sources that define the AA step kernels; ties
+    recorded hardware-counter measurements to the kernel they measured."""
+    import hashlib
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    h = hashlib.sha256()
+    for f in ("lattice.hpp", "collide.hpp", "cumulant.hpp", "step_impl.hpp", "step_q19.hip",
+              "step_q27.hip"):
+        with open(os.path.join(here, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
