@@ -115,6 +115,34 @@ def recorded_traffic(workload_key):
     return None, None
 
 
+def serving_leg(n_requests):
+    """Continuous batching (FP16 deviation storage) against one-at-a-time
+    FP32 solves of the same Poisson trace; time to steady state per request."""
+    from paper_2408_06880_amd import lbm, server
+    budget = 288 * (1 << 30) - 8 * (1 << 30)
+    kw = dict(L_range=(64, 128), phi_range=(0.3, 0.9), tau_range=(0.6, 1.0))
+    trace = server.make_trace(n_requests, 20.0, seed=31, **kw)
+    res, met = server.Server(server.GpuStepper(storage=lbm.STORE_F16DEV), budget, K=100,
+                             tol=1e-6, max_steps=20000).run(trace)
+    log(f"serving (batched f16dev): p50 {met['p50_latency_s']:.3f} s p99 "
+        f"{met['p99_latency_s']:.3f} s, {met['aggregate_mflups']:.0f} MFLUPS")
+    res32, met32 = server.run_sequential(server.GpuStepper(storage=lbm.STORE_F32),
+                                         server.make_trace(n_requests, 20.0, seed=31, **kw),
+                                         K=100, tol=1e-6, max_steps=20000)
+    log(f"serving (sequential f32): p50 {met32['p50_latency_s']:.3f} s p99 "
+        f"{met32['p99_latency_s']:.3f} s, {met32['aggregate_mflups']:.0f} MFLUPS")
+    pk = [abs(a.permeability - b.permeability) / abs(b.permeability)
+          for a, b in zip(res, res32) if b.permeability]
+    keys = ("p50_latency_s", "p99_latency_s", "p50_queue_s", "p99_queue_s", "p50_service_s",
+            "p99_service_s", "aggregate_mflups", "busy_mflups", "makespan_s", "completed",
+            "converged")
+    return {"trace": f"{n_requests} requests, Poisson 20/s, seed 31, L 64-128, phi 0.3-0.9, "
+                     f"tau 0.6-1.0, D3Q19 TRT, residual < 1e-6 (cap 20000 steps)",
+            "batched_f16dev": {k: met[k] for k in keys},
+            "sequential_f32": {k: met32[k] for k in keys},
+            "permeability_rel_diff_f16_vs_f32_max": max(pk) if pk else None}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +159,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
+    ap.add_argument("--serving", type=int, default=12,
+                    help="requests in the serving trace (0: skip the serving leg)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -233,6 +263,10 @@ def main():
         log(f"dense comparator {dense['mflups_fluid']:.0f} MFLUPS (fluid cells)")
         del ds
 
+    serving = None
+    if args.serving > 0:
+        serving = serving_leg(args.serving)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(lab, per, q, args.tau, magic, force, nf, args.cpu_seconds)
@@ -277,6 +311,7 @@ def main():
         "pct_copy_bw": round(100.0 * mflups * 1e6 * b_alg / (copy_gbs * 1e9), 2) if copy_gbs else None,
         "builder_ms": round(build_ms, 2),
         "dense_comparator": dense,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -44,8 +44,13 @@ __device__ __forceinline__ CollParams<R> seg_params(const Seg& g) {
   return p;
 }
 
+#ifndef LBM_STEP_WAVES_PER_EU
+#define LBM_STEP_WAVES_PER_EU 1
+#endif
+
 template <int Q, int COLL, int ST, bool ODD, bool IDX16>
-__global__ __launch_bounds__(256) void k_aa_step(const StepArgs a) {
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU))) void k_aa_step(const StepArgs a) {
   using SP = Store<ST>;
   using T = typename SP::T;
   using R = typename SP::R;

@@ -17,7 +17,9 @@ import os
 import threading
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "liblbm.so")
+# LBM_LIBRARY may point at another build of the same sources (launch-bound
+# variants compared by the tuner); default: the in-tree library.
+LIB_PATH = os.environ.get("LBM_LIBRARY") or os.path.join(_PKG, "liblbm.so")
 
 # ----------------------------------------------------------------- constants
 LBM_OK, LBM_EINVAL, LBM_ERANGE, LBM_ENOMEM = 0, -1, -2, -3

@@ -1,0 +1,309 @@
+"""Continuous-batching server for permeability solves.
+
+Requests (a seeded sphere packing, its size, porosity and relaxation time)
+arrive over time.  The server admits them while the device-memory budget
+allows, keeps every admitted solve resident in HBM, and advances all active
+solves together: one batched launch per AA half-step over the concatenated
+fluid lists (`lbm_step_batch`), K steps per round, then one deterministic FP64
+reduction per solve (`lbm_reduce_batch`).  A solve retires when its
+mean-momentum residual r(n) = |J_x(n) - J_x(n-K)| / |J_x(n)| drops below the
+tolerance (or it hits its step cap); its memory is freed and queued requests
+are admitted at the next round boundary.  Rounds are K steps long with K even,
+so every solve is at even parity when it joins or leaves the batch.
+
+The permeability follows Darcy's law with a body force,
+k = nu * <rho u_x> / F_x over the whole box (nu = (tau - 1/2)/3, lattice
+units).
+
+Backends: `GpuStepper` drives liblbm; `MockStepper` is a host-only stand-in
+with a modelled cost and convergence for testing the scheduler without a GPU.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import math
+import time
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float          # seconds after the trace starts
+    L: int                  # box edge (periodic cube)
+    phi: float              # target porosity
+    seed: int               # geometry seed
+    tau: float              # relaxation time
+    force: float = 1e-6     # body force along x
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    arrival: float
+    admitted: float = math.nan
+    finished: float = math.nan
+    steps: int = 0
+    n_fluid: int = 0
+    permeability: float = math.nan
+    residual: float = math.nan
+    converged: bool = False
+    error: str = ""
+
+    @property
+    def latency(self):
+        return self.finished - self.arrival
+
+
+def make_trace(n, rate_hz, seed=31, L_range=(64, 384), phi_range=(0.3, 0.9),
+               tau_range=(0.6, 1.0), L_step=8):
+    """Poisson arrivals (exponential gaps, mean 1/rate) and uniformly drawn
+    request parameters, all from one seeded generator."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(n):
+        t += rng.exponential(1.0 / rate_hz)
+        L = int(rng.integers(L_range[0] // L_step, L_range[1] // L_step + 1)) * L_step
+        out.append(Request(rid=i, arrival=t, L=L, phi=float(rng.uniform(*phi_range)),
+                           seed=1000 + i, tau=float(rng.uniform(*tau_range))))
+    return out
+
+
+def percentile(xs, p):
+    xs = sorted(xs)
+    if not xs:
+        return math.nan
+    k = (len(xs) - 1) * p / 100.0
+    lo, hi = math.floor(k), math.ceil(k)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+class Server:
+    def __init__(self, stepper, budget_bytes, K=100, tol=1e-6, max_steps=200_000,
+                 max_active=64, clock=time.perf_counter, sleep=time.sleep):
+        if K <= 0 or K % 2:
+            raise ValueError("K must be a positive even number of steps")
+        self.stepper = stepper
+        self.budget = int(budget_bytes)
+        self.K = K
+        self.tol = tol
+        self.max_steps = max_steps
+        self.max_active = max_active
+        self.clock = clock
+        self.sleep = sleep
+
+    def run(self, trace):
+        """Serve `trace` (list of Request) in real time; returns (results,
+        metrics)."""
+        pending = collections.deque(sorted(trace, key=lambda r: r.arrival))
+        queue = collections.deque()
+        active = []       # dicts: req, res, handle, bytes, jx history
+        results = {}
+        used = 0
+        flups = 0
+        t0 = self.clock()
+        busy = 0.0
+        while pending or queue or active:
+            now = self.clock() - t0
+            while pending and pending[0].arrival <= now:
+                r = pending.popleft()
+                queue.append(r)
+                results[r.rid] = Result(rid=r.rid, arrival=r.arrival)
+            # admission: FIFO while the head fits the memory budget
+            while queue and len(active) < self.max_active:
+                r = queue[0]
+                need = self.stepper.bytes_needed(r)
+                if need > self.budget:
+                    queue.popleft()
+                    results[r.rid].error = f"needs {need} bytes > budget {self.budget}"
+                    results[r.rid].finished = self.clock() - t0
+                    continue
+                if used + need > self.budget:
+                    break
+                queue.popleft()
+                handle = self.stepper.build(r)
+                res = results[r.rid]
+                res.admitted = self.clock() - t0
+                res.n_fluid = self.stepper.n_fluid(handle)
+                active.append({"req": r, "res": res, "handle": handle, "bytes": need,
+                               "jx": []})
+                used += need
+            if not active:
+                if pending:
+                    wait = pending[0].arrival - (self.clock() - t0)
+                    if wait > 0:
+                        self.sleep(wait)
+                continue
+            # one round: K lockstep steps for every active solve
+            tb = self.clock()
+            self.stepper.step([a["handle"] for a in active], self.K)
+            red = self.stepper.reduce([a["handle"] for a in active])
+            busy += self.clock() - tb
+            keep = []
+            for a, (jx, finite) in zip(active, red):
+                res = a["res"]
+                res.steps += self.K
+                flups += res.n_fluid * self.K
+                a["jx"].append(jx)
+                done = False
+                if not finite:
+                    res.error = "non-finite state"
+                    done = True
+                elif len(a["jx"]) >= 2 and abs(a["jx"][-1]) > 0:
+                    res.residual = abs(a["jx"][-1] - a["jx"][-2]) / abs(a["jx"][-1])
+                    if res.steps >= 2 * self.K and res.residual < self.tol:
+                        res.converged = True
+                        done = True
+                if res.steps >= self.max_steps:
+                    done = True
+                if done:
+                    r = a["req"]
+                    nu = (r.tau - 0.5) / 3.0
+                    res.permeability = nu * (jx / float(r.L ** 3)) / r.force
+                    res.finished = self.clock() - t0
+                    self.stepper.free(a["handle"])
+                    used -= a["bytes"]
+                else:
+                    keep.append(a)
+            active = keep
+        makespan = self.clock() - t0
+        done = [r for r in results.values() if not r.error]
+        lat = [r.latency for r in done]
+        metrics = {
+            "requests": len(results),
+            "completed": len(done),
+            "converged": sum(r.converged for r in done),
+            "rejected_or_failed": len(results) - len(done),
+            "p50_latency_s": percentile(lat, 50),
+            "p99_latency_s": percentile(lat, 99),
+            "p50_queue_s": percentile([r.admitted - r.arrival for r in done], 50),
+            "p99_queue_s": percentile([r.admitted - r.arrival for r in done], 99),
+            "p50_service_s": percentile([r.finished - r.admitted for r in done], 50),
+            "p99_service_s": percentile([r.finished - r.admitted for r in done], 99),
+            "makespan_s": makespan,
+            "aggregate_mflups": flups / makespan / 1e6 if makespan > 0 else 0.0,
+            "busy_mflups": flups / busy / 1e6 if busy > 0 else 0.0,
+            "fluid_cell_updates": flups,
+        }
+        return [results[k] for k in sorted(results)], metrics
+
+
+class MockStepper:
+    """Host-only backend: a solve of N_F = phi * L^3 cells costs N_F / rate
+    seconds per step on a simulated clock and its momentum approaches a
+    request-specific limit geometrically, so the scheduler can be tested
+    deterministically without a GPU."""
+
+    def __init__(self, rate_flups=1e9, bytes_per_cell=112, decay=0.9, fail_rid=None):
+        self.rate = rate_flups
+        self.bpc = bytes_per_cell
+        self.decay = decay
+        self.fail_rid = fail_rid
+        self.now = 0.0
+        self.live = {}
+        self.built = []
+
+    def clock(self):
+        return self.now
+
+    def sleep(self, dt):
+        self.now += dt
+
+    def bytes_needed(self, r):
+        return int(r.phi * r.L ** 3) * self.bpc
+
+    def build(self, r):
+        h = {"req": r, "nf": int(r.phi * r.L ** 3), "t": 0}
+        self.live[id(h)] = h
+        self.built.append(r.rid)
+        return h
+
+    def n_fluid(self, h):
+        return h["nf"]
+
+    def step(self, hs, n):
+        self.now += sum(h["nf"] for h in hs) * n / self.rate
+        for h in hs:
+            h["t"] += n
+
+    def reduce(self, hs):
+        out = []
+        for h in hs:
+            r = h["req"]
+            limit = r.L * r.phi
+            jx = limit * (1.0 - self.decay ** (h["t"] / 100.0))
+            out.append((jx, r.rid != self.fail_rid))
+        return out
+
+    def free(self, h):
+        del self.live[id(h)]
+
+
+class GpuStepper:
+    """liblbm backend: seeded packing -> GPU builder -> resident solve."""
+
+    def __init__(self, storage=None, q=19, dev_exp=14, order=None, compact=True, magic=3 / 16,
+                 r_range=(4.0, 12.0), stream=None):
+        from . import lbm
+        self.lbm = lbm
+        self.storage = lbm.STORE_F16DEV if storage is None else storage
+        self.q = q
+        self.dev_exp = dev_exp if self.storage == lbm.STORE_F16DEV else 0
+        self.order = lbm.ORDER_BLOCKED if order is None else order
+        self.compact = compact
+        self.magic = magic
+        self.r_range = r_range
+        self.stream = stream
+        import torch
+        self.torch = torch
+        self._ws = None
+
+    def bytes_needed(self, r):
+        """PDF-list, int32 and compact index-lists, reduction workspace, a
+        little slack for the fluid list; from the target porosity."""
+        nf = int(math.ceil(r.phi * r.L ** 3 * 1.02)) + 64
+        b = self.lbm.STORE_BYTES[self.storage]
+        per_cell = self.q * b + (self.q - 1) * 4 + 4
+        if self.compact:
+            per_cell += (self.q - 1) * 2
+        return nf * per_cell + (1 << 20)
+
+    def build(self, r):
+        from .inputs import boolean_spheres, PERIODIC_ALL
+        lab, info = boolean_spheres(r.L, self.r_range[0], self.r_range[1], r.phi, seed=r.seed)
+        dom = self.lbm.SparseDomain(lab, PERIODIC_ALL, self.q, self.order, 64, stream=self.stream)
+        if self.compact:
+            dom.compact(stream=self.stream)
+        sol = self.lbm.Solver(dom, self.storage, self.dev_exp)
+        sol.init(stream=self.stream)
+        coll = self.lbm.collision(self.lbm.COLL_TRT, tau=r.tau, magic=self.magic,
+                                  force=(r.force, 0.0, 0.0))
+        return {"req": r, "sol": sol, "coll": coll}
+
+    def n_fluid(self, h):
+        return h["sol"].domain.n_fluid
+
+    def step(self, hs, n):
+        self.lbm.lbm_step_batch([h["sol"].state for h in hs], [h["coll"] for h in hs], None, n,
+                                self.stream)
+
+    def reduce(self, hs):
+        need = sum(self.lbm.lbm_reduce_workspace_bytes(h["sol"].domain.layout) for h in hs)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = self.torch.empty(max(need, 1 << 16), dtype=self.torch.uint8, device="cuda")
+        red = self.lbm.lbm_reduce_batch([h["sol"].state for h in hs], [h["coll"] for h in hs],
+                                        self._ws, self.stream, check=False)
+        return [(r.mom[0], bool(r.finite)) for r in red]
+
+    def free(self, h):
+        h["sol"] = None
+        h["coll"] = None
+
+
+def run_sequential(stepper, trace, K=100, tol=1e-6, max_steps=200_000):
+    """Baseline: the same trace served one solve at a time (no batching)."""
+    srv = Server(stepper, budget_bytes=1 << 62, K=K, tol=tol, max_steps=max_steps, max_active=1)
+    return srv.run(trace)

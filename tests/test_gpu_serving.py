@@ -1,0 +1,59 @@
+"""GPU tests of the continuous-batching server: every result is the same
+alone and in the mix, and the 16-bit serving path meets the permeability
+error target against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2408_06880_amd import inputs, server
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2408_06880_amd import lbm  # noqa: E402
+
+
+def _trace():
+    reqs = server.make_trace(5, 1000.0, seed=7, L_range=(24, 48), phi_range=(0.4, 0.8))
+    for r in reqs:
+        r.arrival = 0.0
+        r.force = 1e-5
+    return reqs
+
+
+def test_batched_results_equal_alone():
+    """R13: per-cell arithmetic does not depend on the batch, so steps,
+    residuals and permeabilities are bitwise those of each solve alone."""
+    trace = _trace()
+    mixed, met = server.Server(server.GpuStepper(), 1 << 34, K=100, tol=1e-6,
+                               max_steps=3000).run(trace)
+    alone, _ = server.run_sequential(server.GpuStepper(), _trace(), K=100, tol=1e-6,
+                                     max_steps=3000)
+    assert met["completed"] == len(trace)
+    for a, b in zip(mixed, alone):
+        assert (a.rid, a.steps, a.n_fluid, a.converged) == (b.rid, b.steps, b.n_fluid, b.converged)
+        assert a.permeability == b.permeability and a.residual == b.residual
+
+
+@pytest.mark.parametrize("storage,limit", [(lbm.STORE_F32, 1e-5), (lbm.STORE_F16DEV, 1e-3),
+                                           (lbm.STORE_BF16DEV, None)])
+def test_serving_permeability_vs_oracle(storage, limit):
+    """Steady-state permeability of a served request against the FP64 oracle
+    run for the same number of steps (target < 1e-3 relative for 16-bit
+    storage; bfloat16 is reported, not bounded)."""
+    req = server.Request(rid=0, arrival=0.0, L=24, phi=0.55, seed=77, tau=0.8, force=1e-6)
+    res, met = server.Server(server.GpuStepper(storage=storage), 1 << 34, K=100, tol=1e-6,
+                             max_steps=6000).run([req])
+    r = res[0]
+    assert not r.error and r.steps > 0
+    lab, info = inputs.boolean_spheres(24, 4.0, 12.0, 0.55, seed=77)
+    p = oracle.params(q=19, kind=oracle.TRT, tau=0.8, magic=3 / 16, force=(1e-6, 0, 0))
+    A = oracle.dense_run(p, lab, inputs.PERIODIC_ALL, r.steps, oracle.dense_init(19, lab))
+    _, J, nf = oracle.dense_reduce(p, lab, A)
+    k_ref = (0.8 - 0.5) / 3.0 * (J[0] / 24 ** 3) / 1e-6
+    err = abs(r.permeability - k_ref) / abs(k_ref)
+    print(f"[gpu-test] storage {storage}: steps {r.steps} converged {r.converged} "
+          f"residual {r.residual:.2e} k {r.permeability:.6e} ref {k_ref:.6e} rel err {err:.2e}",
+          flush=True)
+    if limit is not None:
+        assert err < limit

@@ -1,0 +1,104 @@
+"""Host-only tests of the serving scheduler (mock backend) and the tuner's
+selection and cache logic."""
+import json
+
+import pytest
+
+from paper_2408_06880_amd import autotune, server
+
+
+class BudgetCheckingStepper(server.MockStepper):
+    def __init__(self, budget, **kw):
+        super().__init__(**kw)
+        self.budget = budget
+        self.peak = 0
+
+    def build(self, r):
+        h = super().build(r)
+        live = sum(self.bytes_needed(x["req"]) for x in self.live.values())
+        self.peak = max(self.peak, live)
+        assert live <= self.budget
+        return h
+
+
+def _run(trace, budget, **kw):
+    st = BudgetCheckingStepper(budget, rate_flups=5e9)
+    srv = server.Server(st, budget, K=100, tol=1e-6, clock=st.clock, sleep=st.sleep, **kw)
+    res, met = srv.run(trace)
+    return st, res, met
+
+
+def test_trace_is_seeded_and_poisson_like():
+    a = server.make_trace(200, 20.0, seed=31)
+    b = server.make_trace(200, 20.0, seed=31)
+    assert [(r.arrival, r.L, r.phi, r.tau) for r in a] == [(r.arrival, r.L, r.phi, r.tau) for r in b]
+    gaps = [y.arrival - x.arrival for x, y in zip(a, a[1:])]
+    assert 0.03 < sum(gaps) / len(gaps) < 0.07
+    assert all(64 <= r.L <= 384 and 0.3 <= r.phi <= 0.9 and 0.6 <= r.tau <= 1.0 for r in a)
+
+
+def test_all_requests_complete_within_budget_in_fifo_order():
+    trace = server.make_trace(40, 50.0, seed=3, L_range=(32, 96))
+    budget = 3 * 112 * 96 ** 3   # about three of the largest requests at a time
+    st, res, met = _run(trace, budget)
+    assert met["completed"] == 40 and met["converged"] == 40
+    assert st.built == sorted(st.built)               # admitted in arrival order
+    assert st.peak <= budget
+    for r in res:
+        assert r.arrival <= r.admitted <= r.finished
+        assert r.steps % 100 == 0 and r.steps >= 200
+    assert met["p50_latency_s"] <= met["p99_latency_s"]
+    assert met["aggregate_mflups"] > 0
+
+
+def test_oversized_request_rejected_others_served():
+    trace = server.make_trace(6, 10.0, seed=4, L_range=(32, 48))
+    big = server.Request(rid=99, arrival=0.01, L=400, phi=0.9, seed=1, tau=0.8)
+    st, res, met = _run(trace + [big], budget=112 * 64 ** 3)
+    err = [r for r in res if r.error]
+    assert [r.rid for r in err] == [99]
+    assert met["completed"] == 6
+
+
+def test_failed_solve_does_not_stop_the_others():
+    trace = server.make_trace(8, 20.0, seed=5, L_range=(32, 64))
+    st = server.MockStepper(rate_flups=5e9, fail_rid=3)
+    srv = server.Server(st, 1 << 40, K=100, clock=st.clock, sleep=st.sleep)
+    res, met = srv.run(trace)
+    assert [r.rid for r in res if r.error] == [3]
+    assert met["completed"] == 7
+
+
+def test_step_cap_and_even_rounds():
+    with pytest.raises(ValueError):
+        server.Server(server.MockStepper(), 1 << 30, K=99)
+    st = server.MockStepper(rate_flups=5e9, decay=0.999999)
+    srv = server.Server(st, 1 << 40, K=100, tol=1e-12, max_steps=1000, clock=st.clock,
+                        sleep=st.sleep)
+    res, met = srv.run(server.make_trace(3, 10.0, seed=6, L_range=(32, 40)))
+    assert all(r.steps == 1000 and not r.converged for r in res)
+
+
+def test_percentiles():
+    assert server.percentile([1, 2, 3, 4], 50) == 2.5
+    assert server.percentile([5], 99) == 5
+    assert server.percentile(list(range(101)), 99) == 99
+
+
+def test_tuner_choice_and_cache(tmp_path):
+    t = {(64, 0): 3.0, (128, 1): 2.0, (256, 1): 2.0, (256, 0): 2.5}
+    assert autotune.choose(t) == (256, 1)
+    res = autotune.tune(lambda k, b, x: 1.0 / b + (0.1 if x == 0 else 0.0) + k)
+    assert res[0][0] == (256, 1) and res[1][0] == (256, 1)
+    path = tmp_path / "launch.json"
+    autotune.save(str(path), {autotune.cache_key("gfx950", 0, 19, 1, 23): {"block": 128,
+                                                                            "xcd_remap": 1}})
+    autotune.save(str(path), {autotune.cache_key("gfx950", 0, 19, 1, 15): {"block": 64,
+                                                                            "xcd_remap": 0}})
+    cache = json.load(open(path))
+    assert len(cache) == 2
+    e = autotune.lookup(cache, "gfx950", 0, 19, 1, n_fluid=10_000_000)   # bucket 23
+    assert e["block"] == 128
+    e = autotune.lookup(cache, "gfx950", 0, 19, 1, n_fluid=40_000)       # bucket 15
+    assert e["block"] == 64
+    assert autotune.lookup(cache, "gfx950", 1, 19, 1, 1000) is None
