@@ -159,6 +159,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
+    ap.add_argument("--scheme", default="aa", choices=["aa", "pull"],
+                    help="aa: in-place AA steps; pull: two-array pull steps (comparison)")
     ap.add_argument("--serving", type=int, default=12,
                     help="requests in the serving trace (0: skip the serving leg)")
     args = ap.parse_args()
@@ -211,17 +213,32 @@ def main():
     parity0 = sol.t & 1
     torch.cuda.synchronize()
     w0 = time.perf_counter()
-    evs[0].record(stream)
-    for s in range(K):
-        lbm.lbm_step(sol.state, 1, coll, None, stream)
-        evs[s + 1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    durs = [evs[s].elapsed_time(evs[s + 1]) / 1e3 for s in range(K)]
-    odd_d = [d for s, d in enumerate(durs) if ((parity0 + s) & 1) == 0]
-    even_d = [d for s, d in enumerate(durs) if ((parity0 + s) & 1) == 1]
-    t_odd = sum(odd_d) / max(len(odd_d), 1)
-    t_even = sum(even_d) / max(len(even_d), 1)
+    if args.scheme == "pull":
+        if K % 2 or sol.t % 2:
+            raise SystemExit("the pull scheme needs an even number of steps and warm-up steps")
+        sol.step_pull(2, coll)
+        torch.cuda.synchronize()
+        evs = evs[:K // 2 + 1]
+        w0 = time.perf_counter()
+        evs[0].record(stream)
+        for s in range(K // 2):
+            sol.step_pull(2, coll, None, stream)
+            evs[s + 1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        t_odd = t_even = sum(evs[s].elapsed_time(evs[s + 1]) / 2e3 for s in range(K // 2)) / (K // 2)
+    else:
+        evs[0].record(stream)
+        for s in range(K):
+            lbm.lbm_step(sol.state, 1, coll, None, stream)
+            evs[s + 1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        durs = [evs[s].elapsed_time(evs[s + 1]) / 1e3 for s in range(K)]
+        odd_d = [d for s, d in enumerate(durs) if ((parity0 + s) & 1) == 0]
+        even_d = [d for s, d in enumerate(durs) if ((parity0 + s) & 1) == 1]
+        t_odd = sum(odd_d) / max(len(odd_d), 1)
+        t_even = sum(even_d) / max(len(even_d), 1)
     mflups = nf * K / wall / 1e6
     b_pdf = lbm.STORE_BYTES[storage]
     b_idx = 2 if index_form == "compact16" else 4
@@ -231,6 +248,9 @@ def main():
         # read their int32 position
         b_odd += (q - 1) * 4 / 256 + (q - 1) * 4 * escaped
         b_alg = 0.5 * (b_odd + b_even)
+    if args.scheme == "pull":   # every step gathers through the index-list
+        b_even = b_odd
+        b_alg = b_odd
     b_alg_int32 = bytes_per_flup(q, b_pdf, 4)[2]
     log(f"timed {K} steps: {wall * 1e3:.2f} ms, {mflups:.0f} MFLUPS; odd {t_odd * 1e6:.1f} us, "
         f"even {t_even * 1e6:.1f} us")
@@ -276,7 +296,8 @@ def main():
     workload = (f"sparse D3Q19 TRT AA, {args.L}^3 periodic overlapping-sphere packing "
                 f"phi={info['phi']:.3f} (r 4-12, seed {info['seed']})")
     traffic, traffic_src = recorded_traffic(
-        f"{workload}; storage={args.storage}; order={args.order}; index={index_form}")
+        f"{workload}; storage={args.storage}; order={args.order}; index={index_form}"
+        + ("; scheme=pull" if args.scheme == "pull" else ""))
     out = {
         "metric": METRIC,
         "value": round(mflups, 1),
@@ -294,13 +315,16 @@ def main():
         "config": {"workload": workload,
                    "n_fluid": nf, "tau": args.tau, "magic": magic, "force": list(force),
                    "storage": args.storage, "order": args.order, "index": index_form,
+                   "scheme": args.scheme,
                    "index_escaped_fraction": escaped,
                    "stride": dom.stride},
         "pct_hbm_peak": round(100.0 * mflups * 1e6 * b_alg / (HBM_PEAK_GBS * 1e9), 2),
         "bytes_per_flup_alg": b_alg,
         "pct_hbm_peak_int32_index_model": round(
             100.0 * mflups * 1e6 * b_alg_int32 / (HBM_PEAK_GBS * 1e9), 2),
-        "roofline": {"bound": "hbm", "kernel": "AA odd step (index gather + collide + scatter)",
+        "roofline": {"bound": "hbm",
+                     "kernel": ("AA odd step (index gather + collide + scatter)"
+                                if args.scheme == "aa" else "pull step (gather + collide + store)"),
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "traffic_source": traffic_src,

@@ -216,6 +216,17 @@ lbm_status lbm_init_equilibrium(lbm_state* state, double rho0, const double* u0,
 lbm_status lbm_step(lbm_state* state, int32_t n_steps, const lbm_collision* coll,
                     const lbm_bspec* bspec, void* stream);
 
+/* Two-array pull scheme over the same lists (the pattern the paper's AA
+ * section compares against): every step gathers through the index-list,
+ * collides and writes f*_i to slot i*S + k of the other array, then the two
+ * arrays swap.  *spare is a device buffer of the same size as state->pdf;
+ * on return state->pdf holds the current populations and *spare the other
+ * buffer.  The slot layout stays natural, so t must be even on entry and
+ * n_steps even (then the state continues seamlessly with lbm_step).  The
+ * launch configuration of LBM_KERNEL_ODD is used.  Errors as lbm_step. */
+lbm_status lbm_step_pull(lbm_state* state, void** spare, int32_t n_steps,
+                         const lbm_collision* coll, const lbm_bspec* bspec, void* stream);
+
 /* Density and velocity of every fluid cell at the current t (either
  * parity), from the post-collision populations: rho = sum f*,
  * u = (sum c f* - F/2) / rho.

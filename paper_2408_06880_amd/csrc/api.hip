@@ -203,10 +203,10 @@ lbm_status link_update(const lbm_state* s, const lbm_bspec* bs, hipStream_t st) 
   return LBM_OK;
 }
 
-hipError_t launch_aa(int q, int coll, int storage, bool odd, bool idx16, const StepArgs& a,
+hipError_t launch_aa(int q, int coll, int storage, int mode, bool idx16, const StepArgs& a,
                      int block, hipStream_t st) {
-  if (q == 19) return launch_aa_q19(coll, storage, odd, idx16, a, block, st);
-  return launch_aa_q27(coll, storage, odd, idx16, a, block, st);
+  if (q == 19) return launch_aa_q19(coll, storage, mode, idx16, a, block, st);
+  return launch_aa_q27(coll, storage, mode, idx16, a, block, st);
 }
 
 uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
@@ -399,7 +399,8 @@ static lbm_status step_group(lbm_state* const* states, const lbm_collision* cons
         }
         a.nseg = ns;
         a.ntiles = tiles;
-        if (ns > 0) HIP_TRY(launch_aa(q, kind, storage, odd, idx16, a, cfg.block, st), "AA step");
+        if (ns > 0)
+          HIP_TRY(launch_aa(q, kind, storage, odd ? 1 : 0, idx16, a, cfg.block, st), "AA step");
       }
       if (!odd) break;
     }
@@ -419,6 +420,43 @@ lbm_status lbm_step(lbm_state* s, int32_t n_steps, const lbm_collision* c, const
   const lbm_collision* carr[1] = {c};
   const lbm_bspec* barr[1] = {bs};
   return step_group(arr, carr, barr, 1, n_steps, (hipStream_t)stream);
+}
+
+lbm_status lbm_step_pull(lbm_state* s, void** spare, int32_t n_steps, const lbm_collision* c,
+                         const lbm_bspec* bs, void* stream) {
+  lbm_status rc = check_state(s);
+  if (rc) return rc;
+  rc = check_coll(c, s->layout.q);
+  if (rc) return rc;
+  if (!spare || (s->layout.n_fluid > 0 && !*spare))
+    return fail(LBM_EINVAL, "pull step needs a second PDF-list");
+  if (n_steps < 0 || (n_steps & 1)) return fail(LBM_EINVAL, "n_steps must be even and >= 0");
+  if (s->t & 1) return fail(LBM_ESTATE, "pull steps need the natural slot layout (even t)");
+  hipStream_t st = (hipStream_t)stream;
+  const lbm_launch cfg = get_cfg(LBM_KERNEL_ODD, s->layout.q, s->storage);
+  const bool idx16 = s->index16 != nullptr;
+  for (int32_t step = 0; step < n_steps; ++step) {
+    rc = link_update(s, bs, st);
+    if (rc) return rc;
+    if (s->layout.n_fluid > 0) {
+      StepArgs a;
+      memset(&a, 0, sizeof(a));
+      a.xcd_remap = cfg.xcd_remap;
+      Seg g = make_seg(s, c);
+      g.dst = *spare;
+      g.tile0 = 0;
+      a.seg[0] = g;
+      a.nseg = 1;
+      a.ntiles = ceil_div(g.nf, (uint64_t)cfg.block);
+      HIP_TRY(launch_aa(s->layout.q, c->kind, s->storage, 2, idx16, a, cfg.block, st),
+              "pull step");
+      void* tmp = s->pdf;
+      s->pdf = *spare;
+      *spare = tmp;
+    }
+    s->t += 1;
+  }
+  return LBM_OK;
 }
 
 lbm_status lbm_step_batch(lbm_state* const* states, const lbm_collision* const* colls,

@@ -9,10 +9,10 @@
 
 namespace lbm {
 
-// AA step kernels (step_q19.hip, step_q27.hip)
-hipError_t launch_aa_q19(int coll, int storage, bool odd, bool idx16, const StepArgs& a,
+// AA step kernels (step_q19.hip, step_q27.hip); mode 0 even, 1 odd, 2 pull
+hipError_t launch_aa_q19(int coll, int storage, int mode, bool idx16, const StepArgs& a,
                          int block, hipStream_t st);
-hipError_t launch_aa_q27(int coll, int storage, bool odd, bool idx16, const StepArgs& a,
+hipError_t launch_aa_q27(int coll, int storage, int mode, bool idx16, const StepArgs& a,
                          int block, hipStream_t st);
 
 // Boundary-class coefficients of one solve, precomputed on the host:

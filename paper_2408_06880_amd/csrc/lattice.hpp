@@ -118,6 +118,7 @@ constexpr uint32_t kMaxOff16 = 0xFFFDu;  // largest stored offset
 
 struct Seg {
   void* pdf;               // PDF-list of this solve
+  void* dst;               // pull scheme only: the second PDF-list written this step
   const int32_t* idx;      // index-list (odd steps), or null when off16 is set
   const uint16_t* off16;   // compact index-list offsets, or null
   const int32_t* base16;   // compact index-list tile bases

@@ -11,6 +11,11 @@
 //   opp(i)*S + k and f*_i is written to i*S + k -- purely local, no index
 //   reads, fully coalesced.
 //
+// pull step (two arrays, Section "In-place Streaming: AA Pattern", the pull
+//   pattern the paper compares against): gather exactly as the odd step,
+//   collide, write f*_i to i*S + k of the second array; every step reads
+//   the index-list.
+//
 // One thread updates one fluid cell; a workgroup covers BLOCK consecutive
 // cells of one segment (solve).  Consecutive list positions are neighbours
 // along the list order (blocked, lexicographic or Morton), so the gathers of
@@ -48,9 +53,12 @@ __device__ __forceinline__ CollParams<R> seg_params(const Seg& g) {
 #define LBM_STEP_WAVES_PER_EU 1
 #endif
 
-template <int Q, int COLL, int ST, bool ODD, bool IDX16>
+enum StepMode { MODE_EVEN = 0, MODE_ODD = 1, MODE_PULL = 2 };
+
+template <int Q, int COLL, int ST, int MODE, bool IDX16>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU))) void k_aa_step(const StepArgs a) {
+  constexpr bool GATHER = MODE != MODE_EVEN;
   using SP = Store<ST>;
   using T = typename SP::T;
   using R = typename SP::R;
@@ -63,7 +71,7 @@ __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU))) void k_aa_step(const
   const uint32_t S = g.S;
   const R sc = R(g.scale), isc = R(g.inv_scale);
   R d[Q];
-  if constexpr (ODD) {
+  if constexpr (GATHER) {
     uint32_t pos[Q];
     pos[0] = k;
     if constexpr (IDX16) {
@@ -103,8 +111,16 @@ __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU))) void k_aa_step(const
 #pragma unroll
     for (int i = 0; i < Q; ++i) d[i] = SP::load(pdf[pos[i]], R(Lattice<Q>::w(i)), isc);
     collide<Q, COLL, R>(d, seg_params<R>(g));
+    if constexpr (MODE == MODE_ODD) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) pdf[pos[i]] = SP::store(d[opp(i)], R(Lattice<Q>::w(i)), sc);
+      for (int i = 0; i < Q; ++i) pdf[pos[i]] = SP::store(d[opp(i)], R(Lattice<Q>::w(i)), sc);
+    } else {
+      T* __restrict__ dst = static_cast<T*>(g.dst);
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        __builtin_nontemporal_store(SP::store(d[i], R(Lattice<Q>::w(i)), sc),
+                                    dst + (size_t)i * S + k);
+    }
   } else {
 #pragma unroll
     for (int i = 0; i < Q; ++i)
@@ -120,27 +136,31 @@ __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU))) void k_aa_step(const
 
 // Host-side dispatch over (collision, storage, parity) for one Q.
 template <int Q, int COLL, int ST>
-inline hipError_t launch_aa_cs(bool odd, bool idx16, const StepArgs& a, int block,
+inline hipError_t launch_aa_cs(int mode, bool idx16, const StepArgs& a, int block,
                                hipStream_t st) {
   dim3 grid(a.ntiles), blk(block);
-  if (odd && idx16)
-    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, true, true>), grid, blk, 0, st, a);
-  else if (odd)
-    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, true, false>), grid, blk, 0, st, a);
+  if (mode == MODE_ODD && idx16)
+    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_ODD, true>), grid, blk, 0, st, a);
+  else if (mode == MODE_ODD)
+    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_ODD, false>), grid, blk, 0, st, a);
+  else if (mode == MODE_PULL && idx16)
+    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_PULL, true>), grid, blk, 0, st, a);
+  else if (mode == MODE_PULL)
+    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_PULL, false>), grid, blk, 0, st, a);
   else
-    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, false, false>), grid, blk, 0, st, a);
+    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_EVEN, false>), grid, blk, 0, st, a);
   return hipGetLastError();
 }
 
 template <int Q, int COLL>
-inline hipError_t launch_aa_c(int storage, bool odd, bool idx16, const StepArgs& a, int block,
+inline hipError_t launch_aa_c(int storage, int mode, bool idx16, const StepArgs& a, int block,
                               hipStream_t st) {
   switch (storage) {
-    case ST_F64: return launch_aa_cs<Q, COLL, ST_F64>(odd, idx16, a, block, st);
-    case ST_F32: return launch_aa_cs<Q, COLL, ST_F32>(odd, idx16, a, block, st);
-    case ST_F16DEV: return launch_aa_cs<Q, COLL, ST_F16DEV>(odd, idx16, a, block, st);
-    case ST_BF16DEV: return launch_aa_cs<Q, COLL, ST_BF16DEV>(odd, idx16, a, block, st);
-    case ST_F32DEV: return launch_aa_cs<Q, COLL, ST_F32DEV>(odd, idx16, a, block, st);
+    case ST_F64: return launch_aa_cs<Q, COLL, ST_F64>(mode, idx16, a, block, st);
+    case ST_F32: return launch_aa_cs<Q, COLL, ST_F32>(mode, idx16, a, block, st);
+    case ST_F16DEV: return launch_aa_cs<Q, COLL, ST_F16DEV>(mode, idx16, a, block, st);
+    case ST_BF16DEV: return launch_aa_cs<Q, COLL, ST_BF16DEV>(mode, idx16, a, block, st);
+    case ST_F32DEV: return launch_aa_cs<Q, COLL, ST_F32DEV>(mode, idx16, a, block, st);
   }
   return hipErrorInvalidValue;
 }

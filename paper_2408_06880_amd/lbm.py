@@ -101,6 +101,8 @@ _SIGS = {
     "lbm_init_equilibrium": (_i32, [ctypes.POINTER(lbm_state), _f64, ctypes.POINTER(_f64), _vp]),
     "lbm_step": (_i32, [ctypes.POINTER(lbm_state), _i32, ctypes.POINTER(lbm_collision),
                         ctypes.POINTER(lbm_bspec), _vp]),
+    "lbm_step_pull": (_i32, [ctypes.POINTER(lbm_state), ctypes.POINTER(_vp), _i32,
+                             ctypes.POINTER(lbm_collision), ctypes.POINTER(lbm_bspec), _vp]),
     "lbm_moments": (_i32, [ctypes.POINTER(lbm_state), ctypes.POINTER(lbm_collision), _i32, _vp,
                            _vp, _vp]),
     "lbm_reduce_workspace_bytes": (_u64, [ctypes.POINTER(lbm_layout)]),
@@ -209,6 +211,16 @@ def lbm_init_equilibrium(state, rho0=1.0, u0=(0.0, 0.0, 0.0), stream=None):
 def lbm_step(state, n_steps, coll, bspec=None, stream=None):
     _call("lbm_step", ctypes.byref(state), int(n_steps), ctypes.byref(coll),
           ctypes.byref(bspec) if bspec is not None else None, _stream(stream))
+
+
+def lbm_step_pull(state, spare_ptr, n_steps, coll, bspec=None, stream=None):
+    """spare_ptr: device address of the second PDF-list; returns the address
+    now holding the other buffer."""
+    sp = _vp(spare_ptr)
+    _call("lbm_step_pull", ctypes.byref(state), ctypes.byref(sp), int(n_steps),
+          ctypes.byref(coll), ctypes.byref(bspec) if bspec is not None else None,
+          _stream(stream))
+    return sp.value
 
 
 def lbm_moments(state, coll, out_f64, rho, u, stream=None):
@@ -391,6 +403,15 @@ class Solver:
 
     def step(self, n, coll, bs=None, stream=None):
         lbm_step(self.state, n, coll, bs, stream)
+
+    def step_pull(self, n, coll, bs=None, stream=None):
+        """n (even) two-array pull steps; allocates the second array once."""
+        import torch
+        if getattr(self, "_spare", None) is None:
+            self._spare = torch.empty_like(self.pdf)
+        bufs = {self.pdf.data_ptr(): self.pdf, self._spare.data_ptr(): self._spare}
+        other = lbm_step_pull(self.state, self._spare.data_ptr(), n, coll, bs, stream)
+        self.pdf, self._spare = bufs[self.state.pdf], bufs[other]
 
     def moments(self, coll, f64=True, stream=None):
         import torch

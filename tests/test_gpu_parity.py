@@ -515,3 +515,35 @@ def test_index16_full_size_packing(packing256, order):
     got, n_esc = _decode_index16(dom)
     assert np.array_equal(got, ref.index.reshape(18, S)[:, :nf])
     assert frac < 0.2
+
+
+# ------------------------------------------------------------ pull scheme
+@pytest.mark.parametrize("compact", [False, True])
+def test_pull_scheme_bitwise_equals_aa(compact):
+    """An AA odd+even pair performs the same collisions on the same inputs
+    as two pull steps (Section "In-place Streaming: AA Pattern"), so after
+    every even step count the two schemes agree bit for bit (links too)."""
+    lab = inputs.random_mask((22, 19, 17), 0.3, seed=6, n_classes=3, class_fraction=0.5)
+    coll, bs, op = _params(19, lbm.COLL_TRT, 0.75, (1e-5, 0, 0), CLASSES)
+    doms = [lbm.SparseDomain(lab, 5, 19, lbm.ORDER_BLOCKED) for _ in range(2)]
+    if compact:
+        for d in doms:
+            d.compact()
+    torch.cuda.synchronize()
+    _check_index(doms[0])
+    a, b = lbm.Solver(doms[0], lbm.STORE_F32), lbm.Solver(doms[1], lbm.STORE_F32)
+    f0 = _random_state(19, doms[0].n_fluid, seed=8)
+    _upload(a, f0, 0)
+    _upload(b, f0, 0)
+    a.step(10, coll, bs)
+    b.step_pull(10, coll, bs)
+    torch.cuda.synchronize()
+    assert a.t == b.t == 10
+    S, nf = doms[0].stride, doms[0].n_fluid
+    pa = a.pdf.view(19, S)[:, :nf]
+    pb = b.pdf.view(19, S)[:, :nf]
+    assert torch.equal(pa, pb)
+    b.step(2, coll, bs)          # continues with AA steps from the pull state
+    a.step(2, coll, bs)
+    torch.cuda.synchronize()
+    assert torch.equal(a.pdf.view(19, S)[:, :nf], b.pdf.view(19, S)[:, :nf])
