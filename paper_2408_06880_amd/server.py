@@ -112,6 +112,7 @@ class Server:
                 r = pending.popleft()
                 queue.append(r)
                 results[r.rid] = Result(rid=r.rid, arrival=r.arrival)
+                self.stepper.prepare(r)   # host-side set-up may start now
             # admission: FIFO while the head fits the memory budget
             while queue and len(active) < self.max_active:
                 r = queue[0]
@@ -215,6 +216,9 @@ class MockStepper:
     def bytes_needed(self, r):
         return int(r.phi * r.L ** 3) * self.bpc
 
+    def prepare(self, r):
+        pass
+
     def build(self, r):
         h = {"req": r, "nf": int(r.phi * r.L ** 3), "t": 0}
         self.live[id(h)] = h
@@ -257,9 +261,23 @@ class GpuStepper:
         self.magic = magic
         self.r_range = r_range
         self.stream = stream
+        import concurrent.futures
         import torch
         self.torch = torch
         self._ws = None
+        # Geometry generation runs on host threads while the GPU steps the
+        # active solves (the blocking GPU calls release the interpreter lock).
+        self._pool = concurrent.futures.ThreadPoolExecutor(max_workers=2)
+        self._labels = {}
+
+    def _geometry(self, r):
+        from .inputs import boolean_spheres
+        lab, _ = boolean_spheres(r.L, self.r_range[0], self.r_range[1], r.phi, seed=r.seed)
+        return lab
+
+    def prepare(self, r):
+        if r.rid not in self._labels:
+            self._labels[r.rid] = self._pool.submit(self._geometry, r)
 
     def bytes_needed(self, r):
         """PDF-list, int32 and compact index-lists, reduction workspace, a
@@ -272,8 +290,9 @@ class GpuStepper:
         return nf * per_cell + (1 << 20)
 
     def build(self, r):
-        from .inputs import boolean_spheres, PERIODIC_ALL
-        lab, info = boolean_spheres(r.L, self.r_range[0], self.r_range[1], r.phi, seed=r.seed)
+        from .inputs import PERIODIC_ALL
+        self.prepare(r)
+        lab = self._labels.pop(r.rid).result()
         dom = self.lbm.SparseDomain(lab, PERIODIC_ALL, self.q, self.order, 64, stream=self.stream)
         if self.compact:
             dom.compact(stream=self.stream)
