@@ -209,54 +209,63 @@ def _capsule_stamp(mask, value, p0, p1, r, only_where=None):
     sub[inside] = value
 
 
-def vessel_tree(n=512, r0=24.0, ratio=0.79, k_len=14.0, seed=7, angle_deg=(20.0, 60.0),
-                r_min=3.0, inlet_u=0.02):
+def vessel_tree(n=512, r0=24.0, ratio=0.79, k_len=6.0, seed=7, angle_deg=(20.0, 60.0),
+                r_min=2.0, inlet_u=0.02, n_azimuth=24, max_depth=16):
     """Synthetic bifurcating vessel tree in a closed box (no periodicity).
 
     Root tube from the inlet disk at z = 0, centred in x-y, along +z, radius
     r0.  Each segment has length k_len * r; its end spawns two daughters of
-    radius ratio*r with polar angles uniform in `angle_deg` from the parent
-    axis and azimuths psi, psi + pi.  A branch stops (outlet) when the
-    daughter radius would drop below r_min or the daughter would leave the
-    box margin.  Tubes are capsules; labels: fluid 0, tissue 1, inlet class
-    0 (label 2) = the z = 0 disk, outlet class 1 (label 3) = a one-cell cap
-    just past each terminal end.
+    radius ratio*r with polar angles drawn uniformly from `angle_deg`
+    (measured from the parent axis) and azimuths psi and psi + pi.  psi is
+    the first of `n_azimuth` seeded candidates for which both daughter
+    segments stay inside the box margin (r + 2 cells); if only one daughter
+    fits any candidate it grows alone.  A branch ends (outlet) when the
+    daughter radius would drop below r_min or no daughter fits.  Tubes are
+    capsules (their union is the lumen).  Labels: fluid 0, tissue 1, inlet
+    class 0 (label 2) = the z = 0 disk, outlet class 1 (label 3) = a one-cell
+    cap just past each terminal end (on tissue only).
     Returns (labels, periodic=0, info)."""
     rng = np.random.default_rng(seed)
     mask = np.ones((n, n, n), np.uint8)  # tissue everywhere
     segs = []
     ends = []
+
+    def inside(p, r):
+        return bool(np.all(p >= r + 2) and np.all(p <= n - r - 2))
+
     stack = [(np.array([n / 2.0, n / 2.0, 0.0]), np.array([0.0, 0.0, 1.0]), r0, 0)]
     while stack:
         p0, axis, r, depth = stack.pop()
         p1 = p0 + axis * k_len * r
         segs.append((p0, p1, r))
         rd = ratio * r
-        margin_ok = np.all(p1 >= r + 2) and np.all(p1 <= n - r - 2)
-        if rd < r_min or not margin_ok or depth > 12:
+        if rd < r_min or depth >= max_depth:
             ends.append((p1, axis, r))
             continue
-        # daughters
-        theta1, theta2 = np.deg2rad(rng.uniform(*angle_deg, size=2))
-        psi = rng.uniform(0.0, 2.0 * np.pi)
-        # orthonormal frame around axis
         tmp = np.array([1.0, 0.0, 0.0]) if abs(axis[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
         e1 = np.cross(axis, tmp)
         e1 /= np.linalg.norm(e1)
         e2 = np.cross(axis, e1)
-        children = []
-        for th, ps in ((theta1, psi), (theta2, psi + np.pi)):
-            dirv = np.cos(th) * axis + np.sin(th) * (np.cos(ps) * e1 + np.sin(ps) * e2)
-            dirv /= np.linalg.norm(dirv)
-            children.append(dirv)
-        leaves = True
-        for dirv in children:
-            tip = p1 + dirv * k_len * rd
-            if np.all(tip >= rd + 2) and np.all(tip <= n - rd - 2):
-                stack.append((p1.copy(), dirv, rd, depth + 1))
-                leaves = False
-        if leaves:
+        th = np.deg2rad(rng.uniform(*angle_deg, size=2))
+        psi0 = rng.uniform(0.0, 2.0 * np.pi)
+        best = None
+        for c in range(n_azimuth):
+            psi = psi0 + 2.0 * np.pi * c / n_azimuth
+            dirs = []
+            for t, ps in ((th[0], psi), (th[1], psi + np.pi)):
+                d = np.cos(t) * axis + np.sin(t) * (np.cos(ps) * e1 + np.sin(ps) * e2)
+                dirs.append(d / np.linalg.norm(d))
+            fits = [inside(p1 + d * k_len * rd, rd) for d in dirs]
+            if all(fits):
+                best = dirs
+                break
+            if best is None and any(fits):
+                best = [d for d, f in zip(dirs, fits) if f]
+        if not best:
             ends.append((p1, axis, r))
+            continue
+        for d in best:
+            stack.append((p1.copy(), d, rd, depth + 1))
     for p0, p1, r in segs:
         _capsule_stamp(mask, 0, p0, p1, r)
     # outlet caps: one-cell-thick disc just past each terminal end, only on tissue
@@ -280,6 +289,12 @@ def workload_c0():
     """32^3 periodic box, non-overlapping spheres r in [3, 5], porosity ~0.6, seed 1."""
     lab, info = rsa_spheres(32, 3.0, 5.0, 0.6, seed=1)
     return lab, PERIODIC_ALL, info
+
+
+def workload_vessel(n=512):
+    """512^3 vessel tree (root radius 24, ratio 0.79, branch angles 20-60 deg),
+    velocity inlet 0.02 along +z at z = 0, pressure outlets (rho = 1)."""
+    return vessel_tree(n=n)
 
 
 def workload_c1(phi=0.6, L=256, seed=None):

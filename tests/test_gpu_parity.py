@@ -547,3 +547,58 @@ def test_pull_scheme_bitwise_equals_aa(compact):
     a.step(2, coll, bs)
     torch.cuda.synchronize()
     assert torch.equal(a.pdf.view(19, S)[:, :nf], b.pdf.view(19, S)[:, :nf])
+
+
+# ------------------------------------------------------------ vessel tree
+def _vessel_params():
+    classes = [(lbm.BC_UBB, (0.0, 0.0, 0.02), 1.0), (lbm.BC_PRESSURE, (0, 0, 0), 1.0)]
+    return _params(27, lbm.COLL_CUMULANT, 0.6, (0.0, 0.0, 0.0), classes)
+
+
+def test_vessel_tree_small_matches_dense_oracle():
+    """A 48^3 tree with the benchmark's branching rules: D3Q27 cumulant FP32
+    with the UBB inlet and pressure outlets, 100 steps, against the dense
+    FP64 oracle."""
+    lab, per, info = inputs.vessel_tree(n=48, r0=5.0, k_len=5.0, r_min=1.5, seed=3)
+    assert info["n_fluid"] > 1000 and (lab == 2).any() and (lab == 3).any()
+    coll, bs, op = _vessel_params()
+    dom = lbm.SparseDomain(lab, per, 27, lbm.ORDER_BLOCKED)
+    dom.compact()
+    torch.cuda.synchronize()
+    _check_index(dom)
+    sol = lbm.Solver(dom, lbm.STORE_F32)
+    sol.init()
+    sol.step(100, coll, bs)
+    A = oracle.dense_run(op, lab, per, 100, oracle.dense_init(27, lab))
+    torch.cuda.synchronize()
+    cells = dom.cells[:dom.n_fluid].cpu().numpy()
+    got = _download(sol, 0)
+    ref = A.reshape(27, -1)[:, cells]
+    assert np.max(np.abs(got - ref) / np.abs(ref)) <= 1e-5
+
+
+def test_vessel_tree_full_size_two_steps():
+    """The 512^3 benchmark tree in the benchmark's launch configuration: one
+    odd and one even step from a perturbed state against the oracle's sparse
+    AA scheme (links included), every fluid cell."""
+    lab, per, info = inputs.workload_vessel()
+    _say("vessel full size", info["n_fluid"], info["n_outlets"])
+    coll, bs, op = _vessel_params()
+    dom = lbm.SparseDomain(lab, per, 27, lbm.ORDER_BLOCKED)
+    dom.compact()
+    torch.cuda.synchronize()
+    sol = lbm.Solver(dom, lbm.STORE_F32)
+    seen = _upload(sol, _random_state(27, dom.n_fluid, seed=2, amp=1e-3), 0)
+    ref_lay = oracle.sparse_build(lab, per, 27, order=2, align=64)
+    assert np.array_equal(ref_lay.cells, dom.cells[:dom.n_fluid].cpu().numpy())
+    assert ref_lay.n_links == dom.n_links
+    pdf = np.zeros(27 * ref_lay.stride)
+    for i in range(27):
+        pdf[i * ref_lay.stride:i * ref_lay.stride + dom.n_fluid] = seen[i]
+    for t in range(2):
+        sol.step(1, coll, bs)
+        pdf = oracle.sparse_run(op, ref_lay, pdf, t, 1)
+        torch.cuda.synchronize()
+        got = _download(sol, 0)
+        ref = oracle.sparse_gather(ref_lay, pdf, t + 1)
+        assert np.max(np.abs(got - ref) / np.abs(ref)) <= 1e-5

@@ -219,3 +219,15 @@ def test_sparse_aa_matches_dense_on_packing():
     got = oracle.sparse_gather(lay, pdf, 100)
     ref = A.reshape(19, -1)[:, lay.cells]
     assert np.max(np.abs(got - ref) / ref) < 1e-14
+
+
+def test_vessel_tree_generator_is_seeded_and_labelled():
+    a, per, ia = inputs.vessel_tree(n=40, r0=4.0, k_len=5.0, r_min=1.5, seed=9)
+    b, _, ib = inputs.vessel_tree(n=40, r0=4.0, k_len=5.0, r_min=1.5, seed=9)
+    assert np.array_equal(a, b) and per == 0
+    assert set(np.unique(a)) <= {0, 1, 2, 3}
+    assert ia["n_fluid"] == int(np.count_nonzero(a == 0)) > 0
+    assert np.all(a[0][a[0] != 1] == 2)            # the z = 0 layer is tissue or inlet
+    lay = oracle.sparse_build(a, per, 27, order=2, align=8)
+    cls = (lay.links[1::2] >> 8) & 0xff
+    assert set(np.unique(cls)) == {0, 1}          # inlet and outlet links both present
