@@ -17,6 +17,8 @@ from __future__ import annotations
 
 import argparse
 import json
+
+import numpy as np
 import os
 import sys
 import time
@@ -143,12 +145,95 @@ def serving_leg(n_requests):
             "permeability_rel_diff_f16_vs_f32_max": max(pk) if pk else None}
 
 
+def _steady_run(lbm, torch, dom, storage, dev_exp, coll, K, tol, cap, L):
+    """Advance a fresh solve in rounds of K steps until the mean-momentum
+    residual drops below tol (or cap); returns its figures."""
+    sol = lbm.Solver(dom, storage, dev_exp)
+    sol.init()
+    jx, res, t_gpu = [], float("nan"), 0.0
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    while sol.t < cap:
+        e0.record()
+        sol.step(K, coll)
+        e1.record()
+        r = sol.reduce(coll)
+        t_gpu += e0.elapsed_time(e1) / 1e3
+        jx.append(r.mom[0])
+        if len(jx) >= 2 and jx[-1] != 0:
+            res = abs(jx[-1] - jx[-2]) / abs(jx[-1])
+            if sol.t >= 2 * K and res < tol:
+                break
+    rho, u = sol.moments(coll, f64=True)
+    nf = dom.n_fluid
+    umax = float(torch.sqrt((u[:, :nf] ** 2).sum(0)).max())
+    nu = (coll.tau - 0.5) / 3.0
+    k = nu * (jx[-1] / float(L ** 3)) / coll.force[0]
+    return {"steps": sol.t, "residual": res, "converged": res < tol, "permeability": k,
+            "max_speed": umax, "mflups": nf * sol.t / t_gpu / 1e6}
+
+
+def mixed_precision_study(L=384, oracle_L=64, K=100, tol=1e-6, cap=20000):
+    """Config 3: the benchmark's packing geometry (overlapping spheres, r 4-12,
+    porosity 0.6) at 384^3 run to steady state with every storage format; permeability and maximum speed
+    against FP64 storage on the GPU at full size and against the FP64 oracle
+    at a reduced size the oracle can converge."""
+    import torch
+
+    import oracle
+    from paper_2408_06880_amd import inputs, lbm
+    fmts = [("f64", lbm.STORE_F64, 0), ("f32", lbm.STORE_F32, 0), ("f32dev", lbm.STORE_F32DEV, 0),
+            ("f16dev", lbm.STORE_F16DEV, 14), ("bf16dev", lbm.STORE_BF16DEV, 0)]
+    coll = lbm.collision(lbm.COLL_TRT, tau=0.8, magic=3 / 16, force=(1e-6, 0.0, 0.0))
+    out = {}
+    for size, tag in ((oracle_L, "oracle_size"), (L, "full_size")):
+        t0 = time.perf_counter()
+        lab, info = inputs.boolean_spheres(size, 4.0, 12.0, 0.6, seed=21)
+        log(f"mixed precision {size}^3: phi {info['phi']:.4f}, n_fluid {info['n_fluid']}, "
+            f"{info['n_spheres']} spheres ({time.perf_counter() - t0:.1f} s)")
+        dom = lbm.SparseDomain(lab, inputs.PERIODIC_ALL, 19, lbm.ORDER_BLOCKED)
+        dom.compact()
+        runs = {}
+        for name, st, e in fmts:
+            runs[name] = _steady_run(lbm, torch, dom, st, e, coll, K, tol, cap, size)
+            log(f"  {name}: {runs[name]}")
+        ref = {"permeability": runs["f64"]["permeability"], "max_speed": runs["f64"]["max_speed"],
+               "source": "FP64 storage on the GPU (itself within 1e-12 of the oracle per step)"}
+        if tag == "oracle_size":
+            p = oracle.params(q=19, kind=oracle.TRT, tau=0.8, magic=3 / 16, force=(1e-6, 0, 0))
+            A = oracle.dense_init(19, lab)
+            jx, steps, res = [], 0, float("nan")
+            while steps < cap:
+                A = oracle.dense_run(p, lab, inputs.PERIODIC_ALL, K, A)
+                steps += K
+                _, J, _ = oracle.dense_reduce(p, lab, A)
+                jx.append(J[0])
+                if len(jx) >= 2:
+                    res = abs(jx[-1] - jx[-2]) / abs(jx[-1])
+                    if steps >= 2 * K and res < tol:
+                        break
+            rho, u = oracle.dense_moments(p, lab, A)
+            fl = lab == 0
+            ref = {"permeability": (0.8 - 0.5) / 3.0 * (jx[-1] / size ** 3) / 1e-6,
+                   "max_speed": float(np.sqrt((u[:, fl] ** 2).sum(0)).max()),
+                   "steps": steps, "residual": res, "source": "FP64 CPU oracle (dense pull)"}
+        for name in runs:
+            runs[name]["permeability_rel_err"] = abs(runs[name]["permeability"] -
+                                                     ref["permeability"]) / abs(ref["permeability"])
+            runs[name]["max_speed_rel_err"] = abs(runs[name]["max_speed"] -
+                                                  ref["max_speed"]) / ref["max_speed"]
+        out[tag] = {"L": size, "phi": info["phi"], "n_fluid": info["n_fluid"], "reference": ref,
+                    "runs": runs}
+        del dom
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="packing", choices=["packing", "vessel"],
+    ap.add_argument("--workload", default="packing", choices=["packing", "vessel", "mixed"],
                     help="packing: D3Q19 TRT 256^3 sphere packing (the metric's workload); "
                          "vessel: D3Q27 cumulant 512^3 vessel tree with inlet/outlets")
     ap.add_argument("--phi", type=float, default=0.6)
@@ -177,6 +262,13 @@ def main():
     import torch
 
     from paper_2408_06880_amd import inputs, lbm
+
+    if args.workload == "mixed":
+        study = mixed_precision_study()
+        print(json.dumps({"metric": "steady-state permeability / max-speed error by storage "
+                                    "format (D3Q19 TRT, overlapping-sphere packing r 4-12, porosity 0.6)",
+                          "n_gpus": 1, "data": "synthetic", "mixed_precision": study}), flush=True)
+        return
 
     storage = {"f64": lbm.STORE_F64, "f32": lbm.STORE_F32, "f16dev": lbm.STORE_F16DEV,
                "bf16dev": lbm.STORE_BF16DEV, "f32dev": lbm.STORE_F32DEV}[args.storage]
@@ -214,7 +306,7 @@ def main():
     nf = dom.n_fluid
     sol = lbm.Solver(dom, storage, dev_exp)
     if vessel:
-        coll = lbm.collision(lbm.COLL_CUMULANT, tau=0.6, omega_bulk=1.0, force=force)
+        coll = lbm.collision(lbm.COLL_CUMULANT, tau=0.8, omega_bulk=1.0, force=force)
     else:
         coll = lbm.collision(lbm.COLL_TRT, tau=args.tau, magic=magic, force=force)
     sol.init()
@@ -311,7 +403,7 @@ def main():
     workload = (f"sparse D3Q19 TRT AA, {args.L}^3 periodic overlapping-sphere packing "
                 f"phi={info['phi']:.3f} (r 4-12, seed {info['seed']})")
     if vessel:
-        workload = (f"sparse D3Q27 cumulant AA (tau 0.6), {args.L}^3 vessel tree "
+        workload = (f"sparse D3Q27 cumulant AA (tau 0.8), {args.L}^3 vessel tree "
                     f"(root r 24, ratio 0.79, seed {info['seed']}, {info['n_outlets']} outlets, "
                     f"phi={info['phi']:.4f}), UBB inlet u_z={info['inlet_u']}, pressure outlets")
     traffic, traffic_src = recorded_traffic(

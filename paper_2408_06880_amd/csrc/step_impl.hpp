@@ -52,6 +52,32 @@ __device__ __forceinline__ CollParams<R> seg_params(const Seg& g) {
 #ifndef LBM_STEP_WAVES_PER_EU
 #define LBM_STEP_WAVES_PER_EU 1
 #endif
+// Cache hints of the gather step (compile-time; measured defaults).
+#ifndef LBM_NT_INDEX
+#define LBM_NT_INDEX 1
+#endif
+#ifndef LBM_NT_GATHER
+#define LBM_NT_GATHER 0
+#endif
+#ifndef LBM_NT_SCATTER
+#define LBM_NT_SCATTER 0
+#endif
+
+template <bool NT, class T>
+__device__ __forceinline__ T ld(const T* p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+
+template <bool NT, class T>
+__device__ __forceinline__ void st(T v, T* p) {
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
 
 enum StepMode { MODE_EVEN = 0, MODE_ODD = 1, MODE_PULL = 2 };
 
@@ -84,7 +110,7 @@ __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU))) void k_aa_step(const
       uint32_t o[Q];
       int32_t b[Q];
 #pragma unroll
-      for (int i = 1; i < Q; ++i) o[i] = __builtin_nontemporal_load(off + (size_t)(i - 1) * S + k);
+      for (int i = 1; i < Q; ++i) o[i] = ld<LBM_NT_INDEX>(off + (size_t)(i - 1) * S + k);
 #pragma unroll
       for (int i = 1; i < Q; ++i) b[i] = base[i - 1];
       bool esc = false;
@@ -106,14 +132,16 @@ __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU))) void k_aa_step(const
       const int32_t* __restrict__ idx = g.idx;
 #pragma unroll
       for (int i = 1; i < Q; ++i)
-        pos[i] = static_cast<uint32_t>(__builtin_nontemporal_load(idx + (size_t)(i - 1) * S + k));
+        pos[i] = static_cast<uint32_t>(ld<LBM_NT_INDEX>(idx + (size_t)(i - 1) * S + k));
     }
 #pragma unroll
-    for (int i = 0; i < Q; ++i) d[i] = SP::load(pdf[pos[i]], R(Lattice<Q>::w(i)), isc);
+    for (int i = 0; i < Q; ++i)
+      d[i] = SP::load(ld<LBM_NT_GATHER>(pdf + pos[i]), R(Lattice<Q>::w(i)), isc);
     collide<Q, COLL, R>(d, seg_params<R>(g));
     if constexpr (MODE == MODE_ODD) {
 #pragma unroll
-      for (int i = 0; i < Q; ++i) pdf[pos[i]] = SP::store(d[opp(i)], R(Lattice<Q>::w(i)), sc);
+      for (int i = 0; i < Q; ++i)
+        st<LBM_NT_SCATTER>(SP::store(d[opp(i)], R(Lattice<Q>::w(i)), sc), pdf + pos[i]);
     } else {
       T* __restrict__ dst = static_cast<T*>(g.dst);
 #pragma unroll

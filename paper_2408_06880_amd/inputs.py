@@ -22,6 +22,7 @@ last sphere may overshoot; the achieved porosity is returned).
 """
 from __future__ import annotations
 
+import collections
 import math
 
 import numpy as np
@@ -81,14 +82,18 @@ def boolean_spheres(L, r_min, r_max, target_phi, seed):
     return mask, info
 
 
-def rsa_spheres(L, r_min, r_max, target_phi, seed, max_rejects=100_000, batch=512):
+def rsa_spheres(L, r_min, r_max, target_phi, seed, max_rejects=100_000, batch=512,
+                window=1 << 18, min_accept=1e-4):
     """Non-overlapping spheres by random sequential addition (periodic box).
 
     A candidate (centre uniform in [0, L)^3, radius uniform in [r_min, r_max])
     is accepted iff its periodic centre distance to every accepted sphere is
-    >= r1 + r2.  Stops when porosity <= target_phi or after `max_rejects`
-    consecutive rejections (jamming).  Candidates are drawn in batches but
-    accepted strictly in draw order, so the result depends only on the seed."""
+    >= r1 + r2.  Stops when porosity <= target_phi, after `max_rejects`
+    consecutive rejections, or when fewer than `min_accept` of the last
+    `window` candidates were accepted (approaching the jamming limit; this
+    test does not depend on the box volume).  Candidates are drawn in
+    batches but accepted strictly in draw order, so the result depends only
+    on the seed."""
     assert 2 * r_max + 2 < L
     rng = np.random.default_rng(seed)
     mask = np.zeros((L, L, L), np.uint8)
@@ -103,6 +108,9 @@ def rsa_spheres(L, r_min, r_max, target_phi, seed, max_rejects=100_000, batch=51
     radii = np.zeros(1024)
     n = 0
     rejects = 0
+    drawn = 0                       # candidates drawn so far
+    acc_hist = collections.deque()  # (drawn, accepted) at batch ends
+    jammed_rate = False
     if nb >= 3:
         offs = np.array([(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)])
     else:
@@ -113,7 +121,14 @@ def rsa_spheres(L, r_min, r_max, target_phi, seed, max_rejects=100_000, batch=51
         d = np.minimum(d, L - d)
         return np.sum(d * d, axis=-1)
 
-    while (total - solid) / total > target_phi and rejects < max_rejects:
+    while (total - solid) / total > target_phi and rejects < max_rejects and not jammed_rate:
+        acc_hist.append((drawn, n))
+        while acc_hist and acc_hist[0][0] < drawn - window:
+            acc_hist.popleft()
+        if drawn >= window and acc_hist and (n - acc_hist[0][1]) < min_accept * (drawn - acc_hist[0][0]):
+            jammed_rate = True
+            break
+        drawn += batch
         cs = rng.uniform(0.0, L, size=(batch, 3))
         rs = rng.uniform(r_min, r_max, size=batch)
         b = np.floor(cs / bin_w).astype(np.int64) % nb
@@ -156,7 +171,7 @@ def rsa_spheres(L, r_min, r_max, target_phi, seed, max_rejects=100_000, batch=51
             solid += _stamp(mask, c, r)
     info = {"kind": "rsa_spheres", "L": L, "r": [r_min, r_max], "target_phi": target_phi,
             "seed": seed, "n_spheres": n, "phi": (total - solid) / total,
-            "n_fluid": total - solid, "jammed": rejects >= max_rejects}
+            "n_fluid": total - solid, "jammed": rejects >= max_rejects or jammed_rate}
     return mask, info
 
 
