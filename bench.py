@@ -254,6 +254,8 @@ def main():
                     help="--workload serving: requests in the trace")
     ap.add_argument("--max-steps", type=int, default=8000,
                     help="--workload serving: step cap per request")
+    ap.add_argument("--target-cells", type=int, default=32_000_000,
+                    help="--workload serving: admit while active fluid cells stay below this")
     ap.add_argument("--serving", type=int, default=12,
                     help="requests in the serving trace (0: skip the serving leg)")
     args = ap.parse_args()
@@ -273,7 +275,8 @@ def main():
         budget = 288 * (1 << 30) - 8 * (1 << 30)
         trace = server.make_trace(args.requests, 20.0, seed=31)
         res, met = server.Server(server.GpuStepper(storage=lbm.STORE_F16DEV), budget, K=100,
-                                 tol=1e-6, max_steps=args.max_steps).run(trace)
+                                 tol=1e-6, max_steps=args.max_steps,
+                                 target_cells=args.target_cells).run(trace)
         work = sum(r.n_fluid * r.steps for r in res)
         capacity_s = work / (met["busy_mflups"] * 1e6) if met["busy_mflups"] else None
         print(json.dumps({
@@ -283,7 +286,8 @@ def main():
             "config": {"workload": f"{args.requests} permeability requests, Poisson 20/s (seed 31), "
                                    "edge U{64..384}, porosity U[0.3,0.9], tau U[0.6,1.0], "
                                    "D3Q19 TRT FP16-deviation storage, residual < 1e-6, "
-                                   f"cap {args.max_steps} steps, 280 GB admission budget"},
+                                   f"cap {args.max_steps} steps, 280 GB admission budget, "
+                                   f"admission while active fluid cells < {args.target_cells}"},
             "serving": met,
             "offered_load_factor": (capacity_s / trace[-1].arrival) if capacity_s else None,
             "requests": [{"rid": r.rid, "L": t.L, "phi": round(t.phi, 3), "n_fluid": r.n_fluid,

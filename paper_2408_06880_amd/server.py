@@ -83,7 +83,11 @@ def percentile(xs, p):
 
 class Server:
     def __init__(self, stepper, budget_bytes, K=100, tol=1e-6, max_steps=200_000,
-                 max_active=64, clock=time.perf_counter, sleep=time.sleep):
+                 max_active=64, target_cells=None, clock=time.perf_counter, sleep=time.sleep):
+        """target_cells: admit new solves only while the active fluid cells
+        stay below this (one solve is always admitted).  Enough cells to
+        saturate the GPU keep throughput, fewer concurrent solves finish
+        sooner; None admits whatever the memory budget allows."""
         if K <= 0 or K % 2:
             raise ValueError("K must be a positive even number of steps")
         self.stepper = stepper
@@ -92,6 +96,7 @@ class Server:
         self.tol = tol
         self.max_steps = max_steps
         self.max_active = max_active
+        self.target_cells = target_cells
         self.clock = clock
         self.sleep = sleep
 
@@ -123,6 +128,10 @@ class Server:
                     results[r.rid].finished = self.clock() - t0
                     continue
                 if used + need > self.budget:
+                    break
+                if (self.target_cells is not None and active and
+                        sum(a["res"].n_fluid for a in active) +
+                        self.stepper.cells_estimate(r) > self.target_cells):
                     break
                 queue.popleft()
                 handle = self.stepper.build(r)
@@ -219,6 +228,9 @@ class MockStepper:
     def prepare(self, r):
         pass
 
+    def cells_estimate(self, r):
+        return int(r.phi * r.L ** 3)
+
     def build(self, r):
         h = {"req": r, "nf": int(r.phi * r.L ** 3), "t": 0}
         self.live[id(h)] = h
@@ -274,6 +286,9 @@ class GpuStepper:
         from .inputs import boolean_spheres
         lab, _ = boolean_spheres(r.L, self.r_range[0], self.r_range[1], r.phi, seed=r.seed)
         return lab
+
+    def cells_estimate(self, r):
+        return int(r.phi * r.L ** 3)
 
     def prepare(self, r):
         if r.rid not in self._labels:

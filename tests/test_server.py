@@ -102,3 +102,15 @@ def test_tuner_choice_and_cache(tmp_path):
     e = autotune.lookup(cache, "gfx950", 0, 19, 1, n_fluid=40_000)       # bucket 15
     assert e["block"] == 64
     assert autotune.lookup(cache, "gfx950", 1, 19, 1, 1000) is None
+
+
+def test_target_cells_limits_concurrency_and_cuts_median_latency():
+    trace = server.make_trace(30, 100.0, seed=8, L_range=(48, 96))
+    lat = {}
+    for tgt in (None, 2 * 96 ** 3):
+        st = server.MockStepper(rate_flups=2e9)
+        srv = server.Server(st, 1 << 40, K=100, target_cells=tgt, clock=st.clock, sleep=st.sleep)
+        res, met = srv.run(trace)
+        assert met["completed"] == 30
+        lat[tgt] = met["p50_latency_s"]
+    assert lat[2 * 96 ** 3] < lat[None]
