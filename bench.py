@@ -148,6 +148,9 @@ def serving_leg(n_requests):
 def _steady_run(lbm, torch, dom, storage, dev_exp, coll, K, tol, cap, L):
     """Advance a fresh solve in rounds of K steps until the mean-momentum
     residual drops below tol (or cap); returns its figures."""
+    if args.pipelined:
+        b, x = lbm.lbm_get_launch(lbm.KERNEL_ODD, q, storage)
+        lbm.lbm_set_launch(lbm.KERNEL_ODD, q, storage, 256, x, 1)
     sol = lbm.Solver(dom, storage, dev_exp)
     sol.init()
     jx, res, t_gpu = [], float("nan"), 0.0
@@ -248,6 +251,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
+    ap.add_argument("--pipelined", type=int, default=0, choices=[0, 1],
+                    help="odd kernel as persistent workgroups prefetching the next tile")
     ap.add_argument("--scheme", default="aa", choices=["aa", "pull"],
                     help="aa: in-place AA steps; pull: two-array pull steps (comparison)")
     ap.add_argument("--requests", type=int, default=48,
@@ -337,6 +342,9 @@ def main():
     torch.cuda.synchronize()
     build_ms = (time.perf_counter() - tb) * 1e3
     nf = dom.n_fluid
+    if args.pipelined:
+        b, x = lbm.lbm_get_launch(lbm.KERNEL_ODD, q, storage)
+        lbm.lbm_set_launch(lbm.KERNEL_ODD, q, storage, 256, x, 1)
     sol = lbm.Solver(dom, storage, dev_exp)
     if vessel:
         coll = lbm.collision(lbm.COLL_CUMULANT, tau=0.8, omega_bulk=1.0, force=force)
@@ -460,7 +468,7 @@ def main():
         "config": {"workload": workload,
                    "n_fluid": nf, "tau": args.tau, "magic": magic, "force": list(force),
                    "storage": args.storage, "order": args.order, "index": index_form,
-                   "scheme": args.scheme,
+                   "scheme": args.scheme, "pipelined_odd": args.pipelined,
                    "index_escaped_fraction": escaped,
                    "stride": dom.stride},
         "pct_hbm_peak": round(100.0 * mflups * 1e6 * b_alg / (HBM_PEAK_GBS * 1e9), 2),

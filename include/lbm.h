@@ -308,7 +308,10 @@ enum { LBM_KERNEL_ODD = 0, LBM_KERNEL_EVEN = 1, LBM_KERNEL_DENSE = 2 };
 typedef struct {
   int32_t block;      /* threads per workgroup: 64, 128 or 256                 */
   int32_t xcd_remap;  /* 1: contiguous tile ranges per XCD (8 XCDs)            */
-  int32_t reserved[2];
+  int32_t pipelined;  /* odd kernel, block 256, compact index-list only: 1 =   */
+                      /* persistent workgroups that load the next tile's       */
+                      /* offsets during the current tile (same results)        */
+  int32_t reserved;
 } lbm_launch;
 
 /* Set / get the launch configuration used for (kernel, q, storage) from

@@ -52,7 +52,8 @@ void launch_defaults() {
       for (auto& c : b) {
         c.block = 256;
         c.xcd_remap = (k == LBM_KERNEL_ODD) ? 1 : 0;
-        c.reserved[0] = c.reserved[1] = 0;
+        c.pipelined = 0;
+        c.reserved = 0;
       }
   g_launch_init = true;
 }
@@ -224,6 +225,8 @@ lbm_status lbm_set_launch(int32_t kernel, int32_t q, int32_t storage, const lbm_
     return fail(LBM_EINVAL, "lbm_set_launch: bad kernel/q/storage");
   if (cfg->block != 64 && cfg->block != 128 && cfg->block != 256)
     return fail(LBM_EINVAL, "block must be 64, 128 or 256 (got %d)", cfg->block);
+  if (cfg->pipelined != 0 && (cfg->pipelined != 1 || kernel != LBM_KERNEL_ODD || cfg->block != 256))
+    return fail(LBM_EINVAL, "pipelined applies to the odd kernel with block 256 only");
   std::lock_guard<std::mutex> lk(g_launch_mu);
   launch_defaults();
   g_launch[kernel][q == 27 ? 1 : 0][storage] = *cfg;
@@ -399,8 +402,8 @@ static lbm_status step_group(lbm_state* const* states, const lbm_collision* cons
         }
         a.nseg = ns;
         a.ntiles = tiles;
-        if (ns > 0)
-          HIP_TRY(launch_aa(q, kind, storage, odd ? 1 : 0, idx16, a, cfg.block, st), "AA step");
+        const int mode = !odd ? 0 : (idx16 && cfg.pipelined == 1 ? 3 : 1);
+        if (ns > 0) HIP_TRY(launch_aa(q, kind, storage, mode, idx16, a, cfg.block, st), "AA step");
       }
       if (!odd) break;
     }

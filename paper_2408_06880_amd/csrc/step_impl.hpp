@@ -79,7 +79,7 @@ __device__ __forceinline__ void st(T v, T* p) {
     *p = v;
 }
 
-enum StepMode { MODE_EVEN = 0, MODE_ODD = 1, MODE_PULL = 2 };
+enum StepMode { MODE_EVEN = 0, MODE_ODD = 1, MODE_PULL = 2, MODE_ODD_PIPE = 3 };
 
 template <int Q, int COLL, int ST, int MODE, bool IDX16>
 __global__ __launch_bounds__(256)
@@ -162,11 +162,116 @@ __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU))) void k_aa_step(const
   }
 }
 
+// Persistent, software-pipelined odd step (compact index-list).  Each
+// workgroup walks tiles v, v + G, v + 2G, ... (G = grid size, a multiple of
+// 8 so that every tile of a workgroup maps to the same XCD range); the
+// offsets of the next tile are loaded before the current tile's gathers,
+// so the index latency of one tile overlaps the gather/collide/scatter of
+// the previous one.  Same arithmetic as k_aa_step<..., MODE_ODD, true>.
+template <int Q>
+__device__ __forceinline__ void pipe_load_offsets(const Seg& g, uint32_t k, uint32_t (&o)[Q]) {
+  if (k < g.nf) {
+#pragma unroll
+    for (int i = 1; i < Q; ++i) o[i] = ld<LBM_NT_INDEX>(g.off16 + (size_t)(i - 1) * g.S + k);
+  }
+}
+
+template <int Q, int COLL, int ST>
+__global__ __launch_bounds__(256) void k_odd_pipe(const StepArgs a) {
+  using SP = Store<ST>;
+  using T = typename SP::T;
+  using R = typename SP::R;
+  const uint32_t G = gridDim.x;
+  uint32_t v = blockIdx.x;
+  if (v >= a.ntiles) return;
+  uint32_t tile = a.xcd_remap ? xcd_tile(v, a.ntiles) : v;
+  int s = seg_of(a, tile);
+  uint32_t o[Q];
+  {
+    const Seg g = a.seg[s];
+    pipe_load_offsets<Q>(g, (tile - g.tile0) * blockDim.x + threadIdx.x, o);
+  }
+  while (true) {
+    const uint32_t vn = v + G;
+    const bool has_next = vn < a.ntiles;
+    uint32_t tn = 0;
+    int sn = 0;
+    uint32_t on[Q];
+    if (has_next) {
+      tn = a.xcd_remap ? xcd_tile(vn, a.ntiles) : vn;
+      sn = seg_of(a, tn);
+      const Seg gn = a.seg[sn];
+      pipe_load_offsets<Q>(gn, (tn - gn.tile0) * blockDim.x + threadIdx.x, on);
+    }
+    {
+      const Seg g = a.seg[s];
+      const uint32_t k = (tile - g.tile0) * blockDim.x + threadIdx.x;
+      if (k < g.nf) {
+        T* __restrict__ pdf = static_cast<T*>(g.pdf);
+        const uint32_t S = g.S;
+        const R sc = R(g.scale), isc = R(g.inv_scale);
+        const uint32_t t16 = ((tile - g.tile0) * blockDim.x) / kTile16;
+        const int32_t* __restrict__ base = g.base16 + (size_t)t16 * (Q - 1);
+        uint32_t pos[Q];
+        int32_t b[Q];
+        pos[0] = k;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) b[i] = base[i - 1];
+        bool esc = false;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+          const uint32_t fl = (uint32_t)((int32_t)((uint32_t)i * S + k) + b[i] + (int32_t)o[i]);
+          const uint32_t bb = (uint32_t)opp(i) * S + k;
+          const uint32_t m = 0u - (uint32_t)(o[i] == kBounce16);
+          pos[i] = (fl & ~m) | (bb & m);
+          esc = esc || o[i] == kEscape16;
+        }
+        if (__ballot(esc)) {
+#pragma unroll
+          for (int i = 1; i < Q; ++i)
+            if (o[i] == kEscape16) pos[i] = (uint32_t)g.idx[(size_t)(i - 1) * S + k];
+        }
+        R d[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+          d[i] = SP::load(ld<LBM_NT_GATHER>(pdf + pos[i]), R(Lattice<Q>::w(i)), isc);
+        collide<Q, COLL, R>(d, seg_params<R>(g));
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+          st<LBM_NT_SCATTER>(SP::store(d[opp(i)], R(Lattice<Q>::w(i)), sc), pdf + pos[i]);
+      }
+    }
+    if (!has_next) break;
+    v = vn;
+    tile = tn;
+    s = sn;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) o[i] = on[i];
+  }
+}
+
 // Host-side dispatch over (collision, storage, parity) for one Q.
 template <int Q, int COLL, int ST>
 inline hipError_t launch_aa_cs(int mode, bool idx16, const StepArgs& a, int block,
                                hipStream_t st) {
   dim3 grid(a.ntiles), blk(block);
+  if (mode == MODE_ODD_PIPE) {
+    // resident workgroups of this kernel, rounded down to a multiple of 8
+    static int resident = 0;
+    if (resident == 0) {
+      int per_cu = 0, dev = 0, cus = 0;
+      hipGetDevice(&dev);
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_odd_pipe<Q, COLL, ST>, 256, 0);
+      resident = per_cu * cus;
+      if (resident < 8) resident = 8;
+    }
+    const int per = resident * 256 / block;
+    uint32_t g = a.ntiles < (uint32_t)per ? a.ntiles : (uint32_t)per;
+    if (g >= 8) g &= ~7u;
+    hipLaunchKernelGGL((k_odd_pipe<Q, COLL, ST>), dim3(g), blk, 0, st, a);
+    return hipGetLastError();
+  }
   if (mode == MODE_ODD && idx16)
     hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_ODD, true>), grid, blk, 0, st, a);
   else if (mode == MODE_ODD)

@@ -76,7 +76,7 @@ class lbm_dense_state(ctypes.Structure):
 
 
 class lbm_launch(ctypes.Structure):
-    _fields_ = [("block", _i32), ("xcd_remap", _i32), ("reserved", _i32 * 2)]
+    _fields_ = [("block", _i32), ("xcd_remap", _i32), ("pipelined", _i32), ("reserved", _i32)]
 
 
 class LbmError(RuntimeError):
@@ -278,15 +278,15 @@ def lbm_dense_step(state, n_steps, coll, stream=None):
           _stream(stream))
 
 
-def lbm_set_launch(kernel, q, storage, block=256, xcd_remap=1):
-    cfg = lbm_launch(block, xcd_remap)
+def lbm_set_launch(kernel, q, storage, block=256, xcd_remap=1, pipelined=0):
+    cfg = lbm_launch(block, xcd_remap, pipelined)
     _call("lbm_set_launch", kernel, q, storage, ctypes.byref(cfg))
 
 
-def lbm_get_launch(kernel, q, storage):
+def lbm_get_launch(kernel, q, storage, full=False):
     cfg = lbm_launch()
     _call("lbm_get_launch", kernel, q, storage, ctypes.byref(cfg))
-    return cfg.block, cfg.xcd_remap
+    return (cfg.block, cfg.xcd_remap, cfg.pipelined) if full else (cfg.block, cfg.xcd_remap)
 
 
 def lbm_copy(dst, src, nbytes, stream=None):

@@ -602,3 +602,31 @@ def test_vessel_tree_full_size_two_steps():
         got = _download(sol, 0)
         ref = oracle.sparse_gather(ref_lay, pdf, t + 1)
         assert np.max(np.abs(got - ref) / np.abs(ref)) <= 1e-5
+
+
+def test_pipelined_odd_kernel_is_bitwise_identical():
+    """The persistent, pipelined odd kernel performs the same per-cell
+    arithmetic: identical PDFs to the one-tile-per-workgroup kernel, also
+    for a batch of solves (tiles of several segments in one launch)."""
+    labs = [inputs.workload_c1(0.6, L=L, seed=L)[0] for L in (64, 72, 96)]
+    coll = lbm.collision(lbm.COLL_TRT, tau=0.7, force=(1e-5, 0, 0))
+    runs = []
+    old = lbm.lbm_get_launch(lbm.KERNEL_ODD, 19, lbm.STORE_F32, full=True)
+    try:
+        for pipelined in (0, 1):
+            lbm.lbm_set_launch(lbm.KERNEL_ODD, 19, lbm.STORE_F32, 256, 1, pipelined)
+            sols = []
+            for lab in labs:
+                dom = lbm.SparseDomain(lab, 7, 19, lbm.ORDER_BLOCKED)
+                assert dom.compact() > 0          # some escaped entries
+                s = lbm.Solver(dom, lbm.STORE_F32)
+                _upload(s, _random_state(19, dom.n_fluid, seed=dom.n_fluid), 0)
+                sols.append(s)
+            sols[2].step(6, coll)
+            lbm.lbm_step_batch([s.state for s in sols[:2]], [coll, coll], None, 6)
+            torch.cuda.synchronize()
+            runs.append([s.pdf.clone() for s in sols])
+    finally:
+        lbm.lbm_set_launch(lbm.KERNEL_ODD, 19, lbm.STORE_F32, *old)
+    for a, b in zip(*runs):
+        assert torch.equal(a, b)
