@@ -245,8 +245,9 @@ def main():
     ap.add_argument("--tau", type=float, default=0.8)
     ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16dev", "bf16dev", "f32dev"])
     ap.add_argument("--order", default="blocked", choices=["morton", "lex", "blocked"])
-    ap.add_argument("--index", default="16", choices=["16", "32"],
-                    help="index-list form: 16 = compact (2 B/entry), 32 = int32")
+    ap.add_argument("--index", default="16", choices=["16", "32", "run"],
+                    help="index-list form: 16 = compact (2 B/entry), 32 = int32, "
+                         "run = run-compressed")
     ap.add_argument("--dense-steps", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -339,6 +340,12 @@ def main():
         escaped = dom.compact()
         index_form = "compact16"
         log(f"compact index-list: {100 * escaped:.2f}% of entries escape to int32")
+    elif args.index == "run":
+        if args.scheme == "pull":
+            raise SystemExit("--scheme pull reads the int32 or 16-bit index-list, not runs")
+        runs_bpc = dom.compact_runs()
+        index_form = "runs"
+        log(f"run-compressed index-list: {runs_bpc:.2f} bytes per fluid cell")
     torch.cuda.synchronize()
     build_ms = (time.perf_counter() - tb) * 1e3
     nf = dom.n_fluid
@@ -395,6 +402,10 @@ def main():
         # one int32 base per direction per 256 cells; escaped entries also
         # read their int32 position
         b_odd += (q - 1) * 4 / 256 + (q - 1) * 4 * escaped
+        b_alg = 0.5 * (b_odd + b_even)
+    elif index_form == "runs":
+        # the whole run form (offsets, masks, values) is read once per odd step
+        b_odd = 2 * q * b_pdf + dom.runs_bytes / nf
         b_alg = 0.5 * (b_odd + b_even)
     if args.scheme == "pull":   # every step gathers through the index-list
         b_even = b_odd

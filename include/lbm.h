@@ -145,6 +145,9 @@ typedef struct {
   const void* index16;   /* device, compact index-list (lbm_compress_index) of  */
                          /* the same index, or NULL; when set, index reads use  */
                          /* it and fall back to `index` for escaped entries     */
+  const void* runs;      /* device, run-compressed index-list (lbm_compress_runs)*/
+                         /* of the same index, or NULL; when set, odd steps read */
+                         /* it instead of index16 and index                     */
   const int32_t* links;  /* device, 2*n_links or NULL when n_links == 0        */
   int64_t t;             /* steps taken. t even: populations in natural slots  */
 } lbm_state;
@@ -199,6 +202,33 @@ typedef struct {
 uint64_t lbm_index16_bytes(const lbm_layout* layout);
 lbm_status lbm_compress_index(const lbm_layout* layout, const int32_t* index, void* index16,
                               uint64_t* n_escaped, void* stream);
+
+/* Run-compressed index-list (same entries as the int32 index-list of
+ * Section "Sparse Data Structure", fewer bytes).  The list positions are
+ * cut into waves of 64 (wave w: positions 64w .. 64w+63, W = ceil(S/64)
+ * waves).  For wave w and direction i a run is a maximal stretch of lanes
+ * whose entries rise by one from lane to lane; it is stored as one int32
+ * v = (entry of its first lane l0) - l0, so that lane l of the run has the
+ * entry v + l.  Rows of a list ordered along x make most entries continue a
+ * run (neighbouring cells pull from neighbouring cells or from consecutive
+ * bounce-back slots), so the form needs a few bytes per cell instead of
+ * 4*(q-1).
+ * Buffer (device), parts 256-byte aligned in this order:
+ *   uint32 voff[W + 1]: index of wave w's first value; voff[W] = all values;
+ *   uint64 mask[W][q-1]: bit l set = lane l starts a run (bit 0 always);
+ *   int32 val[voff[W]]: wave w's values, direction 1's runs in lane order,
+ *                       then direction 2's, ... .
+ *  lbm_runs_header_bytes: bytes of voff and mask (host only).
+ *  lbm_compress_runs: index device int32[(q-1)*S] from lbm_build_sparse;
+ *      runs device buffer of `capacity` >= lbm_runs_header_bytes(layout)
+ *      bytes; *needed (host, required) receives the size of the whole form.
+ *      If capacity >= *needed, writes it and returns LBM_OK; otherwise
+ *      writes voff and mask only and returns LBM_ENOMEM: allocate *needed
+ *      bytes and call again.  SYNC.  lbm_state.index stays required next to
+ *      runs (moments at odd t and the pull step read it). */
+uint64_t lbm_runs_header_bytes(const lbm_layout* layout);
+lbm_status lbm_compress_runs(const lbm_layout* layout, const int32_t* index, void* runs,
+                             uint64_t capacity, uint64_t* needed, void* stream);
 
 /* Initialise every fluid cell to the equilibrium of (rho0, u0) and set
  * state->t = 0.  u0: host double[3].  Padding slots are zeroed (deviation)

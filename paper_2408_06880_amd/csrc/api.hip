@@ -155,6 +155,38 @@ Index16View index16_view(const lbm_layout& L, const void* p) {
   return v;
 }
 
+// Sub-buffers of a run-compressed index-list of `layout` starting at `p`.
+struct RunsView {
+  uint32_t* voff;
+  uint64_t* mask;
+  int32_t* val;
+  uint32_t nw;
+  uint64_t header;
+};
+
+RunsView runs_view(const lbm_layout& L, const void* p) {
+  RunsView v;
+  v.nw = (uint32_t)(((uint64_t)L.stride + kRunWave - 1) / kRunWave);
+  const uint64_t voff_b = align256(4 * ((uint64_t)v.nw + 1));
+  const uint64_t mask_b = align256(8 * (uint64_t)v.nw * (uint64_t)(L.q - 1));
+  v.header = voff_b + mask_b;
+  v.voff = nullptr;
+  v.mask = nullptr;
+  v.val = nullptr;
+  if (p) {
+    char* c = (char*)p;
+    v.voff = (uint32_t*)c;
+    v.mask = (uint64_t*)(c + voff_b);
+    v.val = (int32_t*)(c + v.header);
+  }
+  return v;
+}
+
+// Index form the odd step reads for a state: runs, else compact, else int32.
+int index_form(const lbm_state* s) {
+  return s->runs ? IDX_RUN : (s->index16 ? IDX_16 : IDX_I32);
+}
+
 Seg make_seg(const lbm_state* s, const lbm_collision* c) {
   Seg g;
   memset(&g, 0, sizeof(g));
@@ -167,6 +199,12 @@ Seg make_seg(const lbm_state* s, const lbm_collision* c) {
     g.off16 = v.off;
     g.base16 = v.base;
     g.ntiles16 = v.ntiles;
+  }
+  if (s->runs) {
+    RunsView r = runs_view(s->layout, s->runs);
+    g.rvoff = r.voff;
+    g.rmask = r.mask;
+    g.rval = r.val;
   }
   if (c) {
     coll_rates(c, g.om1, g.om2);
@@ -204,10 +242,10 @@ lbm_status link_update(const lbm_state* s, const lbm_bspec* bs, hipStream_t st) 
   return LBM_OK;
 }
 
-hipError_t launch_aa(int q, int coll, int storage, int mode, bool idx16, const StepArgs& a,
+hipError_t launch_aa(int q, int coll, int storage, int mode, int idx, const StepArgs& a,
                      int block, hipStream_t st) {
-  if (q == 19) return launch_aa_q19(coll, storage, mode, idx16, a, block, st);
-  return launch_aa_q27(coll, storage, mode, idx16, a, block, st);
+  if (q == 19) return launch_aa_q19(coll, storage, mode, idx, a, block, st);
+  return launch_aa_q27(coll, storage, mode, idx, a, block, st);
 }
 
 uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
@@ -216,7 +254,7 @@ uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); 
 
 extern "C" {
 
-int32_t lbm_abi_version(void) { return 1; }
+int32_t lbm_abi_version(void) { return 2; }
 
 const char* lbm_last_error(void) { return g_err.c_str(); }
 
@@ -354,6 +392,44 @@ lbm_status lbm_compress_index(const lbm_layout* L, const int32_t* index, void* i
   return LBM_OK;
 }
 
+// ------------------------------------------- run-compressed index-list
+uint64_t lbm_runs_header_bytes(const lbm_layout* L) {
+  if (!L || (L->q != 19 && L->q != 27) || L->stride < 0) return 0;
+  return runs_view(*L, nullptr).header;
+}
+
+lbm_status lbm_compress_runs(const lbm_layout* L, const int32_t* index, void* runs,
+                             uint64_t capacity, uint64_t* needed, void* stream) {
+  if (!L || !index || !runs || !needed) return fail(LBM_EINVAL, "layout/index/runs/needed is NULL");
+  lbm_status rc = check_layout(*L);
+  if (rc) return rc;
+  RunsView v = runs_view(*L, runs);
+  if (capacity < v.header)
+    return fail(LBM_ENOMEM, "runs buffer of %llu bytes is below the header size %llu",
+                (unsigned long long)capacity, (unsigned long long)v.header);
+  hipStream_t st = (hipStream_t)stream;
+  const uint32_t S = (uint32_t)L->stride;
+  uint32_t total = 0;
+  if (v.nw > 0) {
+    HIP_TRY(launch_runs_mask(L->q, index, S, v.nw, v.mask, v.voff, st), "run masks");
+    HIP_TRY(launch_exclusive_scan(v.nw, v.voff, st), "run offsets");
+    HIP_TRY(hipMemcpyAsync(&total, v.voff + v.nw, 4, hipMemcpyDeviceToHost, st), "run count");
+    HIP_TRY(hipStreamSynchronize(st), "run count sync");
+  } else {
+    HIP_TRY(hipMemsetAsync(v.voff, 0, 4, st), "run offsets");
+    HIP_TRY(hipStreamSynchronize(st), "run offsets sync");
+  }
+  *needed = v.header + 4 * (uint64_t)total;
+  if (capacity < *needed)
+    return fail(LBM_ENOMEM, "runs form needs %llu bytes (capacity %llu)",
+                (unsigned long long)*needed, (unsigned long long)capacity);
+  if (v.nw > 0) {
+    HIP_TRY(launch_runs_emit(L->q, index, S, v.nw, v.voff, v.val, st), "run values");
+    HIP_TRY(hipStreamSynchronize(st), "run values sync");
+  }
+  return LBM_OK;
+}
+
 // ---------------------------------------------------------- stepping
 lbm_status lbm_init_equilibrium(lbm_state* s, double rho0, const double* u0, void* stream) {
   lbm_status rc = check_state(s);
@@ -381,10 +457,9 @@ static lbm_status step_group(lbm_state* const* states, const lbm_collision* cons
       lbm_status rc = link_update(states[j], bspecs ? bspecs[j] : nullptr, st);
       if (rc) return rc;
     }
-    // Odd steps of states with a compact index-list run in launches of
-    // their own (a different kernel); even steps never read indices.
-    for (int form = 0; form < 2; ++form) {
-      const bool idx16 = odd && form == 1;
+    // Odd steps run one launch (group) per index form, each form being a
+    // kernel of its own; even steps never read indices.
+    for (int form = IDX_I32; form <= IDX_RUN; ++form) {
       int32_t j = 0;
       while (j < n) {
         StepArgs a;
@@ -393,8 +468,8 @@ static lbm_status step_group(lbm_state* const* states, const lbm_collision* cons
         uint32_t tiles = 0;
         int ns = 0;
         for (; j < n && ns < kMaxSeg; ++j) {
-          const bool has16 = odd && states[j]->index16 != nullptr;
-          if (states[j]->layout.n_fluid == 0 || has16 != idx16) continue;
+          const int fj = odd ? index_form(states[j]) : IDX_I32;
+          if (states[j]->layout.n_fluid == 0 || fj != form) continue;
           Seg g = make_seg(states[j], colls[j]);
           g.tile0 = tiles;
           tiles += ceil_div(g.nf, (uint64_t)cfg.block);
@@ -402,8 +477,8 @@ static lbm_status step_group(lbm_state* const* states, const lbm_collision* cons
         }
         a.nseg = ns;
         a.ntiles = tiles;
-        const int mode = !odd ? 0 : (idx16 && cfg.pipelined == 1 ? 3 : 1);
-        if (ns > 0) HIP_TRY(launch_aa(q, kind, storage, mode, idx16, a, cfg.block, st), "AA step");
+        const int mode = !odd ? 0 : (form == IDX_16 && cfg.pipelined == 1 ? 3 : 1);
+        if (ns > 0) HIP_TRY(launch_aa(q, kind, storage, mode, form, a, cfg.block, st), "AA step");
       }
       if (!odd) break;
     }
@@ -437,7 +512,8 @@ lbm_status lbm_step_pull(lbm_state* s, void** spare, int32_t n_steps, const lbm_
   if (s->t & 1) return fail(LBM_ESTATE, "pull steps need the natural slot layout (even t)");
   hipStream_t st = (hipStream_t)stream;
   const lbm_launch cfg = get_cfg(LBM_KERNEL_ODD, s->layout.q, s->storage);
-  const bool idx16 = s->index16 != nullptr;
+  // the pull kernel reads the compact or the int32 index-list
+  const int idx = s->index16 ? IDX_16 : IDX_I32;
   for (int32_t step = 0; step < n_steps; ++step) {
     rc = link_update(s, bs, st);
     if (rc) return rc;
@@ -451,7 +527,7 @@ lbm_status lbm_step_pull(lbm_state* s, void** spare, int32_t n_steps, const lbm_
       a.seg[0] = g;
       a.nseg = 1;
       a.ntiles = ceil_div(g.nf, (uint64_t)cfg.block);
-      HIP_TRY(launch_aa(s->layout.q, c->kind, s->storage, 2, idx16, a, cfg.block, st),
+      HIP_TRY(launch_aa(s->layout.q, c->kind, s->storage, 2, idx, a, cfg.block, st),
               "pull step");
       void* tmp = s->pdf;
       s->pdf = *spare;

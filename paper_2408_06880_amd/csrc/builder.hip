@@ -138,10 +138,11 @@ __global__ __launch_bounds__(kBuildBlock) void k_build_count(const BuildArgs b,
   }
 }
 
-// One workgroup: exclusive scan of both count arrays in place.
-__global__ __launch_bounds__(1024) void k_build_scan(uint32_t n, uint32_t* counts) {
+// One workgroup: exclusive scan of narr consecutive count arrays of n + 1
+// words each, in place (totals at [n]).
+__global__ __launch_bounds__(1024) void k_build_scan(uint32_t n, uint32_t* counts, int narr) {
   __shared__ uint64_t sh[1024];
-  for (int arr = 0; arr < 2; ++arr) {
+  for (int arr = 0; arr < narr; ++arr) {
     uint32_t* a = counts + (size_t)arr * (n + 1);
     const uint32_t per = (n + 1023) / 1024;
     const uint32_t lo = threadIdx.x * per;
@@ -257,7 +258,12 @@ hipError_t launch_build_count(const BuildArgs& b, uint32_t* counts, hipStream_t 
 }
 
 hipError_t launch_build_scan(uint32_t n_chunks, uint32_t* counts, hipStream_t st) {
-  hipLaunchKernelGGL(k_build_scan, dim3(1), dim3(1024), 0, st, n_chunks, counts);
+  hipLaunchKernelGGL(k_build_scan, dim3(1), dim3(1024), 0, st, n_chunks, counts, 2);
+  return hipGetLastError();
+}
+
+hipError_t launch_exclusive_scan(uint32_t n, uint32_t* v, hipStream_t st) {
+  hipLaunchKernelGGL(k_build_scan, dim3(1), dim3(1024), 0, st, n, v, 1);
   return hipGetLastError();
 }
 

@@ -10,9 +10,9 @@
 namespace lbm {
 
 // AA step kernels (step_q19.hip, step_q27.hip); mode 0 even, 1 odd, 2 pull
-hipError_t launch_aa_q19(int coll, int storage, int mode, bool idx16, const StepArgs& a,
+hipError_t launch_aa_q19(int coll, int storage, int mode, int idx, const StepArgs& a,
                          int block, hipStream_t st);
-hipError_t launch_aa_q27(int coll, int storage, int mode, bool idx16, const StepArgs& a,
+hipError_t launch_aa_q27(int coll, int storage, int mode, int idx, const StepArgs& a,
                          int block, hipStream_t st);
 
 // Boundary-class coefficients of one solve, precomputed on the host:
@@ -61,6 +61,8 @@ constexpr uint32_t kChunk = kBuildBlock * kCodesPerThread;
 // offsets after the scan, totals at [n_chunks]).
 hipError_t launch_build_count(const BuildArgs& b, uint32_t* counts, hipStream_t st);
 hipError_t launch_build_scan(uint32_t n_chunks, uint32_t* counts, hipStream_t st);
+// Exclusive prefix sum of v[0..n) in place, total at v[n] (one workgroup).
+hipError_t launch_exclusive_scan(uint32_t n, uint32_t* v, hipStream_t st);
 hipError_t launch_build_emit(const BuildArgs& b, const uint32_t* counts, uint32_t S,
                              uint32_t n_fluid, uint32_t n_links, int32_t* cells, int32_t* inv,
                              int32_t* links, hipStream_t st);
@@ -72,6 +74,14 @@ hipError_t launch_build_index(const BuildArgs& b, const int32_t* cells, const in
 hipError_t launch_compress_index(int q, const int32_t* index, uint32_t S, uint32_t nf,
                                  uint32_t ntiles, uint16_t* off, int32_t* base, uint32_t* flags,
                                  hipStream_t st);
+
+// runs.hip: run-compressed index-list.  mask: uint64[nw][q-1]; cnt:
+// uint32[nw+1] (runs per wave, then the exclusive scan of it); val: int32
+// per run.
+hipError_t launch_runs_mask(int q, const int32_t* index, uint32_t S, uint32_t nw, uint64_t* mask,
+                            uint32_t* cnt, hipStream_t st);
+hipError_t launch_runs_emit(int q, const int32_t* index, uint32_t S, uint32_t nw,
+                            const uint32_t* voff, int32_t* val, hipStream_t st);
 
 // dense.hip
 struct DenseArgs {

@@ -116,12 +116,20 @@ constexpr uint16_t kBounce16 = 0xFFFFu;  // upstream cell not fluid
 constexpr uint16_t kEscape16 = 0xFFFEu;  // read the int32 index-list
 constexpr uint32_t kMaxOff16 = 0xFFFDu;  // largest stored offset
 
+// Index-list forms read by the odd step.
+enum IndexForm { IDX_I32 = 0, IDX_16 = 1, IDX_RUN = 2 };
+// Run-compressed index-list: groups of kRunWave list positions (one wave).
+constexpr uint32_t kRunWave = 64;
+
 struct Seg {
   void* pdf;               // PDF-list of this solve
   void* dst;               // pull scheme only: the second PDF-list written this step
   const int32_t* idx;      // index-list (odd steps), or null when off16 is set
   const uint16_t* off16;   // compact index-list offsets, or null
   const int32_t* base16;   // compact index-list tile bases
+  const uint32_t* rvoff;   // run form: first value of each wave, or null
+  const uint64_t* rmask;   // run form: run-start masks [wave][direction]
+  const int32_t* rval;     // run form: run values
   uint32_t ntiles16;       // tiles of the compact index-list
   uint32_t S;              // stride
   uint32_t nf;             // fluid cells

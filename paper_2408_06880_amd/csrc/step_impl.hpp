@@ -81,7 +81,7 @@ __device__ __forceinline__ void st(T v, T* p) {
 
 enum StepMode { MODE_EVEN = 0, MODE_ODD = 1, MODE_PULL = 2, MODE_ODD_PIPE = 3 };
 
-template <int Q, int COLL, int ST, int MODE, bool IDX16>
+template <int Q, int COLL, int ST, int MODE, int IDX>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU))) void k_aa_step(const StepArgs a) {
   constexpr bool GATHER = MODE != MODE_EVEN;
@@ -100,7 +100,26 @@ __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU))) void k_aa_step(const
   if constexpr (GATHER) {
     uint32_t pos[Q];
     pos[0] = k;
-    if constexpr (IDX16) {
+    if constexpr (IDX == IDX_RUN) {
+      // Run form: the wave's run-start masks and first value index are
+      // wave-uniform (scalar loads).  The entry of lane l is the value of
+      // the run holding l plus l; the run's number is the count of run
+      // starts in lanes 1..l (lane 0 always starts one).
+      const uint32_t lane = threadIdx.x & (kRunWave - 1);
+      const uint32_t w = __builtin_amdgcn_readfirstlane(k / kRunWave);
+      const uint64_t* __restrict__ mk = g.rmask + (size_t)w * (Q - 1);
+      const int32_t* __restrict__ val = g.rval + g.rvoff[w];
+      uint32_t vb = 0;
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        const uint64_t m = mk[i - 1];
+        const uint64_t m1 = m >> 1;
+        const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m1 >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m1, 0u));
+        pos[i] = (uint32_t)(ld<LBM_NT_INDEX>(val + vb + r) + (int32_t)lane);
+        vb += (uint32_t)__builtin_popcountll(m);
+      }
+    } else if constexpr (IDX == IDX_16) {
       // All offset loads first, then the tile's bases (the workgroup lies in
       // one compact tile: the block size divides kTile16), then branch-free
       // positions; escaped entries are patched under a wave-uniform branch.
@@ -252,7 +271,7 @@ __global__ __launch_bounds__(256) void k_odd_pipe(const StepArgs a) {
 
 // Host-side dispatch over (collision, storage, parity) for one Q.
 template <int Q, int COLL, int ST>
-inline hipError_t launch_aa_cs(int mode, bool idx16, const StepArgs& a, int block,
+inline hipError_t launch_aa_cs(int mode, int idx, const StepArgs& a, int block,
                                hipStream_t st) {
   dim3 grid(a.ntiles), blk(block);
   if (mode == MODE_ODD_PIPE) {
@@ -272,28 +291,30 @@ inline hipError_t launch_aa_cs(int mode, bool idx16, const StepArgs& a, int bloc
     hipLaunchKernelGGL((k_odd_pipe<Q, COLL, ST>), dim3(g), blk, 0, st, a);
     return hipGetLastError();
   }
-  if (mode == MODE_ODD && idx16)
-    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_ODD, true>), grid, blk, 0, st, a);
+  if (mode == MODE_ODD && idx == IDX_RUN)
+    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_ODD, IDX_RUN>), grid, blk, 0, st, a);
+  else if (mode == MODE_ODD && idx == IDX_16)
+    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_ODD, IDX_16>), grid, blk, 0, st, a);
   else if (mode == MODE_ODD)
-    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_ODD, false>), grid, blk, 0, st, a);
-  else if (mode == MODE_PULL && idx16)
-    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_PULL, true>), grid, blk, 0, st, a);
+    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_ODD, IDX_I32>), grid, blk, 0, st, a);
+  else if (mode == MODE_PULL && idx == IDX_16)
+    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_PULL, IDX_16>), grid, blk, 0, st, a);
   else if (mode == MODE_PULL)
-    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_PULL, false>), grid, blk, 0, st, a);
+    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_PULL, IDX_I32>), grid, blk, 0, st, a);
   else
-    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_EVEN, false>), grid, blk, 0, st, a);
+    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_EVEN, IDX_I32>), grid, blk, 0, st, a);
   return hipGetLastError();
 }
 
 template <int Q, int COLL>
-inline hipError_t launch_aa_c(int storage, int mode, bool idx16, const StepArgs& a, int block,
+inline hipError_t launch_aa_c(int storage, int mode, int idx, const StepArgs& a, int block,
                               hipStream_t st) {
   switch (storage) {
-    case ST_F64: return launch_aa_cs<Q, COLL, ST_F64>(mode, idx16, a, block, st);
-    case ST_F32: return launch_aa_cs<Q, COLL, ST_F32>(mode, idx16, a, block, st);
-    case ST_F16DEV: return launch_aa_cs<Q, COLL, ST_F16DEV>(mode, idx16, a, block, st);
-    case ST_BF16DEV: return launch_aa_cs<Q, COLL, ST_BF16DEV>(mode, idx16, a, block, st);
-    case ST_F32DEV: return launch_aa_cs<Q, COLL, ST_F32DEV>(mode, idx16, a, block, st);
+    case ST_F64: return launch_aa_cs<Q, COLL, ST_F64>(mode, idx, a, block, st);
+    case ST_F32: return launch_aa_cs<Q, COLL, ST_F32>(mode, idx, a, block, st);
+    case ST_F16DEV: return launch_aa_cs<Q, COLL, ST_F16DEV>(mode, idx, a, block, st);
+    case ST_BF16DEV: return launch_aa_cs<Q, COLL, ST_BF16DEV>(mode, idx, a, block, st);
+    case ST_F32DEV: return launch_aa_cs<Q, COLL, ST_F32DEV>(mode, idx, a, block, st);
   }
   return hipErrorInvalidValue;
 }

@@ -48,7 +48,7 @@ class lbm_layout(ctypes.Structure):
 
 class lbm_state(ctypes.Structure):
     _fields_ = [("layout", lbm_layout), ("storage", _i32), ("dev_exp", _i32), ("pdf", _vp),
-                ("index", _vp), ("index16", _vp), ("links", _vp), ("t", _i64)]
+                ("index", _vp), ("index16", _vp), ("runs", _vp), ("links", _vp), ("t", _i64)]
 
 
 class lbm_collision(ctypes.Structure):
@@ -98,6 +98,9 @@ _SIGS = {
     "lbm_index16_bytes": (_u64, [ctypes.POINTER(lbm_layout)]),
     "lbm_compress_index": (_i32, [ctypes.POINTER(lbm_layout), _vp, _vp,
                                   ctypes.POINTER(_u64), _vp]),
+    "lbm_runs_header_bytes": (_u64, [ctypes.POINTER(lbm_layout)]),
+    "lbm_compress_runs": (_i32, [ctypes.POINTER(lbm_layout), _vp, _vp, _u64,
+                                 ctypes.POINTER(_u64), _vp]),
     "lbm_init_equilibrium": (_i32, [ctypes.POINTER(lbm_state), _f64, ctypes.POINTER(_f64), _vp]),
     "lbm_step": (_i32, [ctypes.POINTER(lbm_state), _i32, ctypes.POINTER(lbm_collision),
                         ctypes.POINTER(lbm_bspec), _vp]),
@@ -164,7 +167,10 @@ def _stream(stream):
 
 
 def _ptr(t):
-    return None if t is None else _vp(t.data_ptr())
+    """Device pointer of a tensor (or a raw address given as int)."""
+    if t is None:
+        return None
+    return _vp(t) if isinstance(t, int) else _vp(t.data_ptr())
 
 
 # ------------------------------------------------------ C entry points
@@ -201,6 +207,23 @@ def lbm_compress_index(layout, index, index16, stream=None):
     _call("lbm_compress_index", ctypes.byref(layout), _ptr(index), _ptr(index16),
           ctypes.byref(n), _stream(stream))
     return int(n.value)
+
+
+def lbm_runs_header_bytes(layout):
+    return int(load().lbm_runs_header_bytes(ctypes.byref(layout)))
+
+
+def lbm_compress_runs(layout, index, runs, capacity, stream=None):
+    """Returns (status, needed bytes): status 0 when the whole form was
+    written, LBM_ENOMEM when only the header fitted in `capacity`."""
+    lib = load()
+    need = _u64(0)
+    rc = lib.lbm_compress_runs(ctypes.byref(layout), _ptr(index), _ptr(runs), int(capacity),
+                               ctypes.byref(need), _stream(stream))
+    if rc not in (LBM_OK, LBM_ENOMEM) or (rc == LBM_ENOMEM and need.value == 0):
+        msg = lib.lbm_last_error()
+        raise LbmError("lbm_compress_runs", rc, msg.decode() if msg else "")
+    return int(rc), int(need.value)
 
 
 def lbm_init_equilibrium(state, rho0=1.0, u0=(0.0, 0.0, 0.0), stream=None):
@@ -346,6 +369,7 @@ class SparseDomain:
         self.q = q
         self.periodic = periodic
         self.index16 = None
+        self.runs = None
         del ws
 
     def compact(self, stream=None):
@@ -358,6 +382,23 @@ class SparseDomain:
         self.index16 = buf
         self.escaped = n_esc
         return n_esc / max((self.q - 1) * self.n_fluid, 1)
+
+    def compact_runs(self, stream=None):
+        """Build the run-compressed index-list next to the int32 one (odd
+        steps then read it); returns its size in bytes per fluid cell."""
+        import torch
+        dev = self.index.device
+        hdr = lbm_runs_header_bytes(self.layout)
+        buf = torch.empty(max(hdr, 1), dtype=torch.uint8, device=dev)
+        rc, need = lbm_compress_runs(self.layout, self.index, buf, hdr, stream)
+        if rc != LBM_OK:
+            buf = torch.empty(need, dtype=torch.uint8, device=dev)
+            rc, need2 = lbm_compress_runs(self.layout, self.index, buf, need, stream)
+            if rc != LBM_OK or need2 != need:
+                raise LbmError("lbm_compress_runs", rc, "size changed between calls")
+        self.runs = buf
+        self.runs_bytes = need
+        return need / max(self.n_fluid, 1)
 
     @property
     def n_fluid(self):
@@ -387,6 +428,7 @@ class Solver:
         st.pdf = self.pdf.data_ptr()
         st.index = domain.index.data_ptr()
         st.index16 = domain.index16.data_ptr() if domain.index16 is not None else None
+        st.runs = domain.runs.data_ptr() if domain.runs is not None else None
         st.links = domain.links.data_ptr() if domain.n_links else None
         st.t = 0
         self.state = st

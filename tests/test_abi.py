@@ -27,12 +27,12 @@ def test_library_exports_every_declared_symbol():
     lib = lbm.load()
     for name in declared_functions():
         assert hasattr(lib, name), name
-    assert lbm.lbm_abi_version() == 1
+    assert lbm.lbm_abi_version() == 2
 
 
 def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(lbm.lbm_layout) == 56
-    assert ctypes.sizeof(lbm.lbm_state) == 56 + 8 + 32 + 8
+    assert ctypes.sizeof(lbm.lbm_state) == 56 + 8 + 40 + 8
     assert ctypes.sizeof(lbm.lbm_collision) == 8 + 8 * 6
     assert ctypes.sizeof(lbm.lbm_bspec) == 8 + 8 * 40
     assert ctypes.sizeof(lbm.lbm_reduction) == 48
@@ -49,6 +49,11 @@ def test_workspace_queries():
     assert lbm.lbm_reduce_workspace_bytes(lay) >= 4 * 5 * 8
     lay.q, lay.stride = 19, 1024
     assert lbm.lbm_index16_bytes(lay) >= 18 * 1024 * 2 + 18 * 4 * 4
+    # run form header: uint32 per wave (+1) and uint64 per wave and direction
+    a256 = lambda v: (v + 255) // 256 * 256
+    assert lbm.lbm_runs_header_bytes(lay) == a256(4 * 17) + a256(8 * 16 * 18)
+    lay.q, lay.stride = 27, 1000
+    assert lbm.lbm_runs_header_bytes(lay) == a256(4 * 17) + a256(8 * 16 * 26)
 
 
 def _fake_state(q=19, nf=100, S=128, storage=lbm.STORE_F32):
@@ -82,6 +87,11 @@ def test_invalid_arguments_rejected_on_host():
     expect(lbm.LBM_EINVAL, lbm.lbm_step, _fake_state(), -1, lbm.collision(), None, 0)
     expect(lbm.LBM_EINVAL, lbm.lbm_set_launch, lbm.KERNEL_ODD, 19, lbm.STORE_F32, 100, 1)
     expect(lbm.LBM_EINVAL, lbm.lbm_set_launch, 7, 19, lbm.STORE_F32, 256, 1)
+    lay = _fake_state().layout
+    expect(lbm.LBM_EINVAL, lbm.lbm_compress_runs, lay, None, 16, 1 << 20, 0)
+    # a buffer below the header size is refused before any device work
+    expect(lbm.LBM_ENOMEM, lbm.lbm_compress_runs, lay, 16, 16,
+           lbm.lbm_runs_header_bytes(lay) - 1, 0)
 
 
 def test_batch_mismatch_rejected_on_host():

@@ -517,6 +517,167 @@ def test_index16_full_size_packing(packing256, order):
     assert frac < 0.2
 
 
+# --------------------------------------------- run-compressed index-list
+def _decode_runs(dom):
+    """Host decode of the run-compressed index-list (layout documented in
+    lbm.h): entries of every list position k < S, shape (q-1, S)."""
+    q, S = dom.q, dom.stride
+    raw = dom.runs.cpu().numpy()
+    a256 = lambda v: (v + 255) // 256 * 256
+    nw = (S + 63) // 64
+    voff = raw[:4 * (nw + 1)].view(np.uint32).astype(np.int64)
+    m0 = a256(4 * (nw + 1))
+    mask = raw[m0:m0 + 8 * nw * (q - 1)].view(np.uint64).reshape(nw, q - 1)
+    v0 = m0 + a256(8 * nw * (q - 1))
+    val = raw[v0:v0 + 4 * int(voff[nw])].view(np.int32).astype(np.int64)
+    assert dom.runs_bytes == v0 + 4 * int(voff[nw])
+    bits = np.unpackbits(mask.view(np.uint8).reshape(nw, q - 1, 8), axis=2,
+                         bitorder="little").astype(bool)            # [w][dir][lane]
+    assert bits[:, :, 0].all()                                     # lane 0 starts a run
+    counts = bits.sum(axis=2)                                      # runs per wave, direction
+    first = voff[:nw, None] + np.concatenate(
+        [np.zeros((nw, 1), np.int64), np.cumsum(counts, axis=1)[:, :-1]], axis=1)
+    run = np.cumsum(bits, axis=2) - 1                              # run of each lane
+    lane = np.arange(64)
+    ent = val[first[:, :, None] + run] + lane                     # [w][dir][lane]
+    assert int(voff[nw]) == int(counts.sum())
+    return ent.transpose(1, 0, 2).reshape(q - 1, nw * 64)[:, :S]
+
+
+@pytest.mark.parametrize("order", [lbm.ORDER_BLOCKED, lbm.ORDER_LEX, lbm.ORDER_MORTON])
+@pytest.mark.parametrize("q", [19, 27])
+def test_runs_decode_to_int32_table(order, q):
+    """Every entry, padding included, decodes to the int32 index-list; the
+    stride is not a multiple of 64 here (align 8), so the last wave is
+    partial."""
+    for seed in range(2 * q + order, 2 * q + order + 64):
+        lab = inputs.random_mask((37, 30, 27), 0.35, seed=seed, n_classes=2,
+                                 class_fraction=0.3)
+        dom = lbm.SparseDomain(lab, 5, q, order, align=8)
+        if dom.stride % 64 != 0:
+            break
+    bpc = dom.compact_runs()
+    torch.cuda.synchronize()
+    S = dom.stride
+    assert S % 64 != 0
+    ref = dom.index[:(q - 1) * S].cpu().numpy().reshape(q - 1, S).astype(np.int64)
+    got = _decode_runs(dom)
+    assert np.array_equal(got, ref)
+    assert bpc < 4 * (q - 1)
+
+
+def test_runs_capacity_protocol():
+    """A header-sized buffer gets the size of the whole form and LBM_ENOMEM;
+    a buffer of that size gets the form."""
+    lab = inputs.random_mask((20, 18, 16), 0.3, seed=9)
+    dom = lbm.SparseDomain(lab, 7, 19, lbm.ORDER_BLOCKED)
+    hdr = lbm.lbm_runs_header_bytes(dom.layout)
+    buf = torch.zeros(hdr, dtype=torch.uint8, device="cuda")
+    rc, need = lbm.lbm_compress_runs(dom.layout, dom.index, buf, hdr)
+    assert rc == lbm.LBM_ENOMEM and need > hdr
+    buf = torch.zeros(need, dtype=torch.uint8, device="cuda")
+    rc, need2 = lbm.lbm_compress_runs(dom.layout, dom.index, buf, need)
+    assert rc == lbm.LBM_OK and need2 == need
+
+
+@pytest.mark.parametrize("q,kind,storage", [(27, lbm.COLL_CUMULANT, lbm.STORE_F32),
+                                            (19, lbm.COLL_TRT, lbm.STORE_F64),
+                                            (19, lbm.COLL_SRT, lbm.STORE_F16DEV)])
+def test_runs_steps_bitwise_equal_to_int32(q, kind, storage):
+    """The run form changes how positions are stored, not which: PDFs,
+    moments (also at odd t) and reductions are bitwise those of the int32
+    path, with boundary links."""
+    lab = inputs.random_mask((30, 28, 26), 0.3, seed=5, n_classes=3, class_fraction=0.5)
+    coll, bs, _ = _params(q, kind, 0.7, (1e-5, 0, 0), CLASSES)
+    d32 = lbm.SparseDomain(lab, 3, q, lbm.ORDER_BLOCKED)
+    dr = lbm.SparseDomain(lab, 3, q, lbm.ORDER_BLOCKED)
+    dr.compact_runs()
+    torch.cuda.synchronize()
+    dev_exp = 14 if storage == lbm.STORE_F16DEV else 0
+    a = lbm.Solver(d32, storage, dev_exp)
+    b = lbm.Solver(dr, storage, dev_exp)
+    a.init()
+    b.init()
+    nf = d32.n_fluid
+    for n in (1, 10):
+        a.step(n, coll, bs)
+        b.step(n, coll, bs)
+        torch.cuda.synchronize()
+        assert torch.equal(a.pdf, b.pdf)
+        ra, ua = a.moments(coll)
+        rb, ub = b.moments(coll)
+        assert torch.equal(ra[:nf], rb[:nf]) and torch.equal(ua[:, :nf], ub[:, :nf])
+        xa, xb = a.reduce(coll), b.reduce(coll)
+        assert (xa.mass, tuple(xa.mom)) == (xb.mass, tuple(xb.mom))
+
+
+def test_runs_batch_mixes_index_forms():
+    """One batch holding int32, compact and run-form solves (one launch per
+    form on odd steps) gives each solve the PDFs it gets alone."""
+    labs = [inputs.workload_c1(0.6, L=L, seed=L + 1)[0] for L in (40, 48, 56)]
+    coll = lbm.collision(lbm.COLL_TRT, tau=0.7, force=(1e-5, 0, 0))
+    out = []
+    for batched in (False, True):
+        sols = []
+        for j, lab in enumerate(labs):
+            dom = lbm.SparseDomain(lab, 7, 19, lbm.ORDER_BLOCKED)
+            if j == 1:
+                dom.compact()
+            elif j == 2:
+                dom.compact_runs()
+            s = lbm.Solver(dom, lbm.STORE_F32)
+            _upload(s, _random_state(19, dom.n_fluid, seed=j + 1), 0)
+            sols.append(s)
+        if batched:
+            lbm.lbm_step_batch([s.state for s in sols], [coll] * 3, None, 5)
+        else:
+            for s in sols:
+                s.step(5, coll)
+        torch.cuda.synchronize()
+        out.append([s.pdf.clone() for s in sols])
+    for x, y in zip(*out):
+        assert torch.equal(x, y)
+
+
+def test_runs_empty_and_single_cell():
+    lab = np.ones((4, 4, 4), np.uint8)
+    dom = lbm.SparseDomain(lab, 7, 19)
+    assert dom.compact_runs() > 0            # the header alone
+    sol = lbm.Solver(dom, lbm.STORE_F32)
+    sol.init()
+    sol.step(3, lbm.collision())
+    lab[1, 2, 3] = 0
+    dom = lbm.SparseDomain(lab, 7, 19)
+    dom.compact_runs()
+    torch.cuda.synchronize()
+    assert np.array_equal(_decode_runs(dom),
+                          dom.index[:18 * dom.stride].cpu().numpy().reshape(18, -1))
+    c = lbm.collision(lbm.COLL_SRT, tau=0.9, force=(1e-3, 0, 0))
+    sol = lbm.Solver(dom, lbm.STORE_F64)
+    sol.init()
+    sol.step(4, c)
+    assert abs(sol.reduce(c).mass - 1.0) < 1e-15
+
+
+@pytest.mark.parametrize("order", [2, 1])
+def test_runs_full_size_packing(packing256, order):
+    """The benchmark geometry: the run form decodes to the oracle's int32
+    index-list and needs under 10 bytes per fluid cell (36 for 16-bit
+    offsets, 72 for int32)."""
+    lab, per, info, _ = packing256
+    ref = oracle.sparse_build(lab, per, 19, order=order, align=64)
+    dom = lbm.SparseDomain(lab, per, 19, order)
+    bpc = dom.compact_runs()
+    torch.cuda.synchronize()
+    _say("run form bytes per cell", order, bpc)
+    nf, S = ref.n_fluid, ref.stride
+    assert dom.n_fluid == nf and dom.stride == S
+    got = _decode_runs(dom)
+    assert np.array_equal(got[:, :nf], ref.index.reshape(18, S)[:, :nf])
+    if order == 2:
+        assert bpc < 10
+
+
 # ------------------------------------------------------------ pull scheme
 @pytest.mark.parametrize("compact", [False, True])
 def test_pull_scheme_bitwise_equals_aa(compact):
