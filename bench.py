@@ -194,7 +194,7 @@ def mixed_precision_study(L=384, oracle_L=64, K=100, tol=1e-6, cap=20000):
         log(f"mixed precision {size}^3: phi {info['phi']:.4f}, n_fluid {info['n_fluid']}, "
             f"{info['n_spheres']} spheres ({time.perf_counter() - t0:.1f} s)")
         dom = lbm.SparseDomain(lab, inputs.PERIODIC_ALL, 19, lbm.ORDER_BLOCKED)
-        dom.compact()
+        dom.compact_runs()
         runs = {}
         for name, st, e in fmts:
             runs[name] = _steady_run(lbm, torch, dom, st, e, coll, K, tol, cap, size)
@@ -245,7 +245,7 @@ def main():
     ap.add_argument("--tau", type=float, default=0.8)
     ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16dev", "bf16dev", "f32dev"])
     ap.add_argument("--order", default="blocked", choices=["morton", "lex", "blocked"])
-    ap.add_argument("--index", default="16", choices=["16", "32", "run"],
+    ap.add_argument("--index", default="run", choices=["16", "32", "run"],
                     help="index-list form: 16 = compact (2 B/entry), 32 = int32, "
                          "run = run-compressed")
     ap.add_argument("--dense-steps", type=int, default=200)

@@ -52,7 +52,9 @@ __device__ __forceinline__ CollParams<R> seg_params(const Seg& g) {
 #ifndef LBM_STEP_WAVES_PER_EU
 #define LBM_STEP_WAVES_PER_EU 1
 #endif
-// Cache hints of the gather step (compile-time; measured defaults).
+// Cache hints of the gather step (compile-time; measured defaults).  The
+// index hint covers the int32 and 16-bit forms; run values stay cached
+// (lanes of a run and neighbouring directions share their lines).
 #ifndef LBM_NT_INDEX
 #define LBM_NT_INDEX 1
 #endif
@@ -116,7 +118,7 @@ __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU))) void k_aa_step(const
         const uint64_t m1 = m >> 1;
         const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m1 >> 32),
                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m1, 0u));
-        pos[i] = (uint32_t)(ld<LBM_NT_INDEX>(val + vb + r) + (int32_t)lane);
+        pos[i] = (uint32_t)(val[vb + r] + (int32_t)lane);
         vb += (uint32_t)__builtin_popcountll(m);
       }
     } else if constexpr (IDX == IDX_16) {

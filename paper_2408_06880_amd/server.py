@@ -261,7 +261,7 @@ class MockStepper:
 class GpuStepper:
     """liblbm backend: seeded packing -> GPU builder -> resident solve."""
 
-    def __init__(self, storage=None, q=19, dev_exp=14, order=None, compact=True, magic=3 / 16,
+    def __init__(self, storage=None, q=19, dev_exp=14, order=None, index="runs", magic=3 / 16,
                  r_range=(4.0, 12.0), stream=None):
         from . import lbm
         self.lbm = lbm
@@ -269,7 +269,9 @@ class GpuStepper:
         self.q = q
         self.dev_exp = dev_exp if self.storage == lbm.STORE_F16DEV else 0
         self.order = lbm.ORDER_BLOCKED if order is None else order
-        self.compact = compact
+        if index not in ("runs", "16", "32"):
+            raise ValueError(f"index form must be 'runs', '16' or '32' (got {index!r})")
+        self.index = index
         self.magic = magic
         self.r_range = r_range
         self.stream = stream
@@ -295,22 +297,28 @@ class GpuStepper:
             self._labels[r.rid] = self._pool.submit(self._geometry, r)
 
     def bytes_needed(self, r):
-        """PDF-list, int32 and compact index-lists, reduction workspace, a
-        little slack for the fluid list; from the target porosity."""
+        """PDF-list, int32 index-list and its compressed form, reduction
+        workspace, a little slack for the fluid list; from the target
+        porosity.  The run form is sized for one run start in four entries
+        (packings measure about one in twelve)."""
         nf = int(math.ceil(r.phi * r.L ** 3 * 1.02)) + 64
         b = self.lbm.STORE_BYTES[self.storage]
         per_cell = self.q * b + (self.q - 1) * 4 + 4
-        if self.compact:
+        if self.index == "16":
             per_cell += (self.q - 1) * 2
-        return nf * per_cell + (1 << 20)
+        elif self.index == "runs":
+            per_cell += (self.q - 1) * (8 / 64 + 4 / 4)
+        return int(nf * per_cell) + (1 << 20)
 
     def build(self, r):
         from .inputs import PERIODIC_ALL
         self.prepare(r)
         lab = self._labels.pop(r.rid).result()
         dom = self.lbm.SparseDomain(lab, PERIODIC_ALL, self.q, self.order, 64, stream=self.stream)
-        if self.compact:
+        if self.index == "16":
             dom.compact(stream=self.stream)
+        elif self.index == "runs":
+            dom.compact_runs(stream=self.stream)
         sol = self.lbm.Solver(dom, self.storage, self.dev_exp)
         sol.init(stream=self.stream)
         coll = self.lbm.collision(self.lbm.COLL_TRT, tau=r.tau, magic=self.magic,
