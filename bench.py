@@ -254,6 +254,9 @@ def main():
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--pipelined", type=int, default=0, choices=[0, 1],
                     help="odd kernel as persistent workgroups prefetching the next tile")
+    ap.add_argument("--even-cells", type=int, default=0, choices=[0, 1, 2],
+                    help="cells per thread of the even-step kernel (0: the library's "
+                         "default, two for 16-bit storage)")
     ap.add_argument("--scheme", default="aa", choices=["aa", "pull"],
                     help="aa: in-place AA steps; pull: two-array pull steps (comparison)")
     ap.add_argument("--requests", type=int, default=48,
@@ -352,6 +355,9 @@ def main():
     if args.pipelined:
         b, x = lbm.lbm_get_launch(lbm.KERNEL_ODD, q, storage)
         lbm.lbm_set_launch(lbm.KERNEL_ODD, q, storage, 256, x, 1)
+    if args.even_cells:
+        b, x = lbm.lbm_get_launch(lbm.KERNEL_EVEN, q, storage)
+        lbm.lbm_set_launch(lbm.KERNEL_EVEN, q, storage, b, x, 0, args.even_cells)
     sol = lbm.Solver(dom, storage, dev_exp)
     if vessel:
         coll = lbm.collision(lbm.COLL_CUMULANT, tau=0.8, omega_bulk=1.0, force=force)
@@ -480,6 +486,8 @@ def main():
                    "n_fluid": nf, "tau": args.tau, "magic": magic, "force": list(force),
                    "storage": args.storage, "order": args.order, "index": index_form,
                    "scheme": args.scheme, "pipelined_odd": args.pipelined,
+                   "even_cells_per_thread": lbm.lbm_get_launch(lbm.KERNEL_EVEN, q, storage,
+                                                               full=True)[3],
                    "index_escaped_fraction": escaped,
                    "stride": dom.stride},
         "pct_hbm_peak": round(100.0 * mflups * 1e6 * b_alg / (HBM_PEAK_GBS * 1e9), 2),

@@ -341,7 +341,9 @@ typedef struct {
   int32_t pipelined;  /* odd kernel, block 256, compact index-list only: 1 =   */
                       /* persistent workgroups that load the next tile's       */
                       /* offsets during the current tile (same results)        */
-  int32_t reserved;
+  int32_t cells_per_thread; /* even kernel: 2 = two neighbouring cells per    */
+                      /* thread with 2-wide loads/stores; 0 or 1 = one cell     */
+                      /* (the only choice for the other kernels)              */
 } lbm_launch;
 
 /* Set / get the launch configuration used for (kernel, q, storage) from

@@ -2,11 +2,12 @@
 
 For each kernel kind (odd step, even step, dense comparator) of a given
 (stencil, storage) pair, time every candidate (workgroup size x XCD-aware tile
-order) on a representative solve and keep the fastest.  Results go to a JSON
-cache keyed by device, kernel, stencil, storage and a fluid-cell size bucket;
-`apply()` loads a cache and installs the entries through `lbm_set_launch`.
-The arithmetic does not depend on the launch configuration (each thread still
-updates one cell), so tuning changes speed only.
+order, and for the even step one or two cells per thread) on a representative
+solve and keep the fastest.  Results go to a JSON cache keyed by device,
+kernel, stencil, storage and a fluid-cell size bucket; `apply()` loads a cache
+and installs the entries through `lbm_set_launch`.  The arithmetic does not
+depend on the launch configuration (every candidate performs each cell's
+update with the same instructions), so tuning changes speed only.
 """
 from __future__ import annotations
 
@@ -16,6 +17,7 @@ import os
 
 BLOCKS = (64, 128, 256)
 XCD = (0, 1)
+CELLS = (1, 2)          # cells per thread, even-step kernel only
 KERNEL_NAMES = {0: "odd", 1: "even", 2: "dense"}
 
 
@@ -29,22 +31,29 @@ def cache_key(device: str, kernel: int, q: int, storage: int, bucket: int) -> st
 
 
 def choose(timings: dict) -> tuple:
-    """timings: {(block, xcd): seconds} -> fastest (block, xcd); ties keep the
-    larger block (fewer workgroups), then XCD order on."""
+    """timings: {(block, xcd[, cells]): seconds} -> the fastest configuration;
+    ties keep the larger block (fewer workgroups), then XCD order on, then
+    fewer cells per thread."""
     best = None
     for cfg, t in timings.items():
-        key = (t, -cfg[0], -cfg[1])
+        key = (t, -cfg[0], -cfg[1], *cfg[2:])
         if best is None or key < best[0]:
             best = (key, cfg)
     return best[1]
 
 
-def tune(measure, kernels=(0, 1), blocks=BLOCKS, xcds=XCD):
-    """measure(kernel, block, xcd) -> seconds per launch.  Returns
-    {kernel: ((block, xcd), {cfg: seconds})}."""
+def candidates(kernel, blocks=BLOCKS, xcds=XCD, cells=CELLS):
+    """(block, xcd, cells per thread) candidates of one kernel kind."""
+    cs = cells if kernel == 1 else (1,)
+    return [(b, x, c) for b in blocks for x in xcds for c in cs]
+
+
+def tune(measure, kernels=(0, 1), blocks=BLOCKS, xcds=XCD, cells=CELLS):
+    """measure(kernel, block, xcd, cells) -> seconds per launch.  Returns
+    {kernel: ((block, xcd, cells), {cfg: seconds})}."""
     out = {}
     for k in kernels:
-        timings = {(b, x): float(measure(k, b, x)) for b in blocks for x in xcds}
+        timings = {cfg: float(measure(k, *cfg)) for cfg in candidates(k, blocks, xcds, cells)}
         out[k] = (choose(timings), timings)
     return out
 
@@ -56,9 +65,9 @@ def gpu_measure(solver, coll, steps=8):
 
     from . import lbm
 
-    def measure(kernel, block, xcd):
+    def measure(kernel, block, xcd, cells=1):
         q, st = solver.domain.q, solver.storage
-        lbm.lbm_set_launch(kernel, q, st, block, xcd)
+        lbm.lbm_set_launch(kernel, q, st, block, xcd, 0, cells)
         solver.step(2, coll)
         torch.cuda.synchronize()
         evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps + 1)]
@@ -90,11 +99,12 @@ def tune_solver(solver, coll, cache_path=None, steps=8):
     dev = device_name()
     q, st, nf = solver.domain.q, solver.storage, solver.domain.n_fluid
     entries = {}
-    for k, ((b, x), timings) in res.items():
-        lbm.lbm_set_launch(k, q, st, b, x)
+    for k, ((b, x, c), timings) in res.items():
+        lbm.lbm_set_launch(k, q, st, b, x, 0, c)
         entries[cache_key(dev, k, q, st, size_bucket(nf))] = {
-            "block": b, "xcd_remap": x,
-            "timings_us": {f"{bb}/{xx}": round(t * 1e6, 2) for (bb, xx), t in timings.items()}}
+            "block": b, "xcd_remap": x, "cells_per_thread": c,
+            "timings_us": {"/".join(map(str, cfg)): round(t * 1e6, 2)
+                           for cfg, t in timings.items()}}
     if cache_path:
         save(cache_path, entries)
     return res
@@ -143,6 +153,7 @@ def apply(cache_path, q, storage, n_fluid, device=None):
     for k in (lbm.KERNEL_ODD, lbm.KERNEL_EVEN, lbm.KERNEL_DENSE):
         e = lookup(cache, device, k, q, storage, n_fluid)
         if e is not None:
-            lbm.lbm_set_launch(k, q, storage, e["block"], e["xcd_remap"])
+            lbm.lbm_set_launch(k, q, storage, e["block"], e["xcd_remap"], 0,
+                               e.get("cells_per_thread", 1))
             n += 1
     return n

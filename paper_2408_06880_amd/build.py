@@ -25,6 +25,9 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # packed FP32 instructions are disabled on purpose
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds fuse per source expression only, so every kernel that
+    # inlines the same collision code computes the same bits
+    "-ffp-contract=on",
     "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function",
     f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}",
 ]

@@ -43,17 +43,22 @@ std::mutex g_launch_mu;
 lbm_launch g_launch[3][2][5];  // kernel x (q19, q27) x storage
 bool g_launch_init = false;
 
+bool is16(int s);
+
 void launch_defaults() {
   if (g_launch_init) return;
   // Measured on MI355X: the gather/scatter (odd) kernel gains from keeping
-  // neighbouring tiles on one XCD; the streaming kernels do not.
+  // neighbouring tiles on one XCD; the streaming kernels do not.  The even
+  // kernel takes two cells per thread for 16-bit storage (2-byte lanes),
+  // one otherwise.
   for (int k = 0; k < 3; ++k)
     for (auto& b : g_launch[k])
-      for (auto& c : b) {
+      for (int st = 0; st < 5; ++st) {
+        lbm_launch& c = b[st];
         c.block = 256;
         c.xcd_remap = (k == LBM_KERNEL_ODD) ? 1 : 0;
         c.pipelined = 0;
-        c.reserved = 0;
+        c.cells_per_thread = (k == LBM_KERNEL_EVEN && is16(st)) ? 2 : 1;
       }
   g_launch_init = true;
 }
@@ -265,6 +270,10 @@ lbm_status lbm_set_launch(int32_t kernel, int32_t q, int32_t storage, const lbm_
     return fail(LBM_EINVAL, "block must be 64, 128 or 256 (got %d)", cfg->block);
   if (cfg->pipelined != 0 && (cfg->pipelined != 1 || kernel != LBM_KERNEL_ODD || cfg->block != 256))
     return fail(LBM_EINVAL, "pipelined applies to the odd kernel with block 256 only");
+  if (cfg->cells_per_thread < 0 || cfg->cells_per_thread > 2 ||
+      (cfg->cells_per_thread == 2 && kernel != LBM_KERNEL_EVEN))
+    return fail(LBM_EINVAL, "cells_per_thread must be 0, 1, or 2 for the even kernel (got %d)",
+                cfg->cells_per_thread);
   std::lock_guard<std::mutex> lk(g_launch_mu);
   launch_defaults();
   g_launch[kernel][q == 27 ? 1 : 0][storage] = *cfg;
@@ -459,6 +468,7 @@ static lbm_status step_group(lbm_state* const* states, const lbm_collision* cons
     }
     // Odd steps run one launch (group) per index form, each form being a
     // kernel of its own; even steps never read indices.
+    const uint32_t cpt = (!odd && cfg.cells_per_thread == 2) ? 2 : 1;
     for (int form = IDX_I32; form <= IDX_RUN; ++form) {
       int32_t j = 0;
       while (j < n) {
@@ -472,12 +482,12 @@ static lbm_status step_group(lbm_state* const* states, const lbm_collision* cons
           if (states[j]->layout.n_fluid == 0 || fj != form) continue;
           Seg g = make_seg(states[j], colls[j]);
           g.tile0 = tiles;
-          tiles += ceil_div(g.nf, (uint64_t)cfg.block);
+          tiles += ceil_div(g.nf, (uint64_t)cfg.block * cpt);
           a.seg[ns++] = g;
         }
         a.nseg = ns;
         a.ntiles = tiles;
-        const int mode = !odd ? 0 : (form == IDX_16 && cfg.pipelined == 1 ? 3 : 1);
+        const int mode = !odd ? (cpt == 2 ? 4 : 0) : (form == IDX_16 && cfg.pipelined == 1 ? 3 : 1);
         if (ns > 0) HIP_TRY(launch_aa(q, kind, storage, mode, form, a, cfg.block, st), "AA step");
       }
       if (!odd) break;

@@ -81,7 +81,29 @@ __device__ __forceinline__ void st(T v, T* p) {
     *p = v;
 }
 
-enum StepMode { MODE_EVEN = 0, MODE_ODD = 1, MODE_PULL = 2, MODE_ODD_PIPE = 3 };
+// Run form: the wave's run-start masks and first value index are
+// wave-uniform (scalar loads).  The entry of lane l is the value of the run
+// holding l plus l; the run's number is the count of run starts in lanes
+// 1..l (lane 0 always starts one).
+template <int Q>
+__device__ __forceinline__ void run_positions(const Seg& g, uint32_t k, uint32_t (&pos)[Q]) {
+  const uint32_t lane = threadIdx.x & (kRunWave - 1);
+  const uint32_t w = __builtin_amdgcn_readfirstlane(k / kRunWave);
+  const uint64_t* __restrict__ mk = g.rmask + (size_t)w * (Q - 1);
+  const int32_t* __restrict__ val = g.rval + g.rvoff[w];
+  uint32_t vb = 0;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const uint64_t m = mk[i - 1];
+    const uint64_t m1 = m >> 1;
+    const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m1 >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m1, 0u));
+    pos[i] = (uint32_t)(val[vb + r] + (int32_t)lane);
+    vb += (uint32_t)__builtin_popcountll(m);
+  }
+}
+
+enum StepMode { MODE_EVEN = 0, MODE_ODD = 1, MODE_PULL = 2, MODE_ODD_PIPE = 3, MODE_EVEN2 = 4 };
 
 template <int Q, int COLL, int ST, int MODE, int IDX>
 __global__ __launch_bounds__(256)
@@ -103,24 +125,7 @@ __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU))) void k_aa_step(const
     uint32_t pos[Q];
     pos[0] = k;
     if constexpr (IDX == IDX_RUN) {
-      // Run form: the wave's run-start masks and first value index are
-      // wave-uniform (scalar loads).  The entry of lane l is the value of
-      // the run holding l plus l; the run's number is the count of run
-      // starts in lanes 1..l (lane 0 always starts one).
-      const uint32_t lane = threadIdx.x & (kRunWave - 1);
-      const uint32_t w = __builtin_amdgcn_readfirstlane(k / kRunWave);
-      const uint64_t* __restrict__ mk = g.rmask + (size_t)w * (Q - 1);
-      const int32_t* __restrict__ val = g.rval + g.rvoff[w];
-      uint32_t vb = 0;
-#pragma unroll
-      for (int i = 1; i < Q; ++i) {
-        const uint64_t m = mk[i - 1];
-        const uint64_t m1 = m >> 1;
-        const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m1 >> 32),
-                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m1, 0u));
-        pos[i] = (uint32_t)(val[vb + r] + (int32_t)lane);
-        vb += (uint32_t)__builtin_popcountll(m);
-      }
+      run_positions<Q>(g, k, pos);
     } else if constexpr (IDX == IDX_16) {
       // All offset loads first, then the tile's bases (the workgroup lies in
       // one compact tile: the block size divides kTile16), then branch-free
@@ -181,6 +186,48 @@ __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU))) void k_aa_step(const
       __builtin_nontemporal_store(SP::store(d[i], R(Lattice<Q>::w(i)), sc),
                                   pdf + (size_t)i * S + k);
   }
+}
+
+// Even step, two neighbouring cells per thread: every load and store moves a
+// 2-vector (cells k, k+1 of one direction block), twice the bytes per
+// memory instruction of the one-cell kernel.  v[j] holds slot j of both
+// cells; cell k's results replace the .x halves once collided (its inputs
+// are then dead), cell k+1's the .y halves.  When n_fluid is odd the last
+// pair's second cell is a padding slot (k+1 < stride): it collides its own
+// finite padding values, which only padding reads.
+template <int Q, int COLL, int ST>
+__global__ __launch_bounds__(256) void k_even_pair(const StepArgs a) {
+  using SP = Store<ST>;
+  using T = typename SP::T;
+  using R = typename SP::R;
+  typedef T T2 __attribute__((ext_vector_type(2)));
+  const uint32_t tile = a.xcd_remap ? xcd_tile(blockIdx.x, a.ntiles) : blockIdx.x;
+  const int s = seg_of(a, tile);
+  const Seg g = a.seg[s];
+  const uint32_t k = 2 * ((tile - g.tile0) * blockDim.x + threadIdx.x);
+  if (k >= g.nf) return;
+  T* __restrict__ pdf = static_cast<T*>(g.pdf);
+  const uint32_t S = g.S;
+  const R sc = R(g.scale), isc = R(g.inv_scale);
+  const CollParams<R> p = seg_params<R>(g);
+  T2 v[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j)
+    v[j] = __builtin_nontemporal_load(reinterpret_cast<const T2*>(pdf + (size_t)j * S + k));
+  R d[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) d[i] = SP::load(v[opp(i)].x, R(Lattice<Q>::w(i)), isc);
+  collide<Q, COLL, R>(d, p);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) v[i].x = SP::store(d[i], R(Lattice<Q>::w(i)), sc);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) d[i] = SP::load(v[opp(i)].y, R(Lattice<Q>::w(i)), isc);
+  collide<Q, COLL, R>(d, p);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) v[i].y = SP::store(d[i], R(Lattice<Q>::w(i)), sc);
+#pragma unroll
+  for (int j = 0; j < Q; ++j)
+    __builtin_nontemporal_store(v[j], reinterpret_cast<T2*>(pdf + (size_t)j * S + k));
 }
 
 // Persistent, software-pipelined odd step (compact index-list).  Each
@@ -291,6 +338,10 @@ inline hipError_t launch_aa_cs(int mode, int idx, const StepArgs& a, int block,
     uint32_t g = a.ntiles < (uint32_t)per ? a.ntiles : (uint32_t)per;
     if (g >= 8) g &= ~7u;
     hipLaunchKernelGGL((k_odd_pipe<Q, COLL, ST>), dim3(g), blk, 0, st, a);
+    return hipGetLastError();
+  }
+  if (mode == MODE_EVEN2) {
+    hipLaunchKernelGGL((k_even_pair<Q, COLL, ST>), grid, blk, 0, st, a);
     return hipGetLastError();
   }
   if (mode == MODE_ODD && idx == IDX_RUN)

@@ -105,10 +105,17 @@ def test_batch_mismatch_rejected_on_host():
 
 
 def test_launch_table_roundtrip():
-    old = lbm.lbm_get_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F16DEV)
+    old = lbm.lbm_get_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F16DEV, full=True)
+    assert old == (256, 0, 0, 2)          # 16-bit storage: two cells per thread
+    assert lbm.lbm_get_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F32, full=True) == (256, 0, 0, 1)
+    assert lbm.lbm_get_launch(lbm.KERNEL_ODD, 19, lbm.STORE_F32, full=True) == (256, 1, 0, 1)
     lbm.lbm_set_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F16DEV, 128, 0)
     assert lbm.lbm_get_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F16DEV) == (128, 0)
     lbm.lbm_set_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F16DEV, *old)
+    assert lbm.lbm_get_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F16DEV, full=True) == old
+    # two cells per thread exist for the even kernel only
+    expect(lbm.LBM_EINVAL, lbm.lbm_set_launch, lbm.KERNEL_ODD, 19, lbm.STORE_F32, 256, 1, 0, 2)
+    expect(lbm.LBM_EINVAL, lbm.lbm_set_launch, lbm.KERNEL_EVEN, 19, lbm.STORE_F32, 256, 0, 0, 3)
 
 
 def test_header_compiles_as_c_and_cxx(tmp_path):

@@ -791,3 +791,44 @@ def test_pipelined_odd_kernel_is_bitwise_identical():
         lbm.lbm_set_launch(lbm.KERNEL_ODD, 19, lbm.STORE_F32, *old)
     for a, b in zip(*runs):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("q,kind,storage", [(19, lbm.COLL_TRT, lbm.STORE_F32),
+                                            (19, lbm.COLL_SRT, lbm.STORE_F16DEV),
+                                            (19, lbm.COLL_TRT, lbm.STORE_F64),
+                                            (27, lbm.COLL_CUMULANT, lbm.STORE_BF16DEV)])
+def test_even_kernel_two_cells_per_thread_is_bitwise_identical(q, kind, storage):
+    """The even kernel with two cells per thread performs each cell's
+    arithmetic unchanged: identical PDFs to one cell per thread, alone and
+    in a batch, with boundary links and an odd fluid-cell count (the last
+    pair ends in a padding slot)."""
+    lab = inputs.random_mask((23, 21, 19), 0.3, seed=12, n_classes=3, class_fraction=0.5)
+    if np.count_nonzero(lab == 0) % 2 == 0:       # make the fluid-cell count odd
+        lab[np.unravel_index(np.flatnonzero(lab == 1)[0], lab.shape)] = 0
+    coll, bs, _ = _params(q, kind, 0.7, (1e-5, 0, 0), CLASSES)
+    dev_exp = 14 if storage == lbm.STORE_F16DEV else 0
+    old = lbm.lbm_get_launch(lbm.KERNEL_EVEN, q, storage, full=True)
+    out = []
+    try:
+        for cpt in (1, 2):
+            lbm.lbm_set_launch(lbm.KERNEL_EVEN, q, storage, 256, 0, 0, cpt)
+            doms = [lbm.SparseDomain(lab, 3, q, lbm.ORDER_BLOCKED),
+                    lbm.SparseDomain(lab[:, :, 1:], 3, q, lbm.ORDER_BLOCKED)]
+            sols = []
+            for j, d in enumerate(doms):
+                d.compact_runs()
+                s = lbm.Solver(d, storage, dev_exp)
+                _upload(s, _random_state(q, d.n_fluid, seed=j + 4), dev_exp)
+                sols.append(s)
+            assert doms[0].n_fluid % 2 == 1
+            sols[0].step(6, coll, bs)
+            lbm.lbm_step_batch([s.state for s in sols], [coll, coll], [bs, bs], 5)
+            torch.cuda.synchronize()
+            out.append([s.pdf[:q * s.domain.stride].view(q, -1)[:, :s.domain.n_fluid].clone()
+                        for s in sols])
+    finally:
+        lbm.lbm_set_launch(lbm.KERNEL_EVEN, q, storage, *old)
+    for a, b in zip(*out):
+        d = (a.double() - b.double()).abs()
+        bad = torch.nonzero(d)
+        assert torch.equal(a, b), (float(d.max()), bad.shape[0], bad[:5].tolist())

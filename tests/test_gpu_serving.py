@@ -60,8 +60,8 @@ def test_serving_permeability_vs_oracle(storage, limit):
 
 
 def test_tuner_installs_a_measured_configuration(tmp_path):
-    """The tuner times every (block, XCD order) candidate on a real solve,
-    installs the fastest and caches it; results do not depend on it."""
+    """The tuner times every (block, XCD order, cells per thread) candidate
+    on a real solve, installs the fastest and caches it."""
     from paper_2408_06880_amd import autotune
     lab, per, info = inputs.workload_c1(0.6, L=96, seed=5)
     dom = lbm.SparseDomain(lab, per, 19, lbm.ORDER_BLOCKED)
@@ -69,15 +69,16 @@ def test_tuner_installs_a_measured_configuration(tmp_path):
     sol = lbm.Solver(dom, lbm.STORE_F32)
     sol.init()
     coll = lbm.collision(lbm.COLL_TRT, tau=0.8, force=(1e-6, 0, 0))
-    old = [lbm.lbm_get_launch(k, 19, lbm.STORE_F32) for k in (0, 1)]
+    old = [lbm.lbm_get_launch(k, 19, lbm.STORE_F32, full=True) for k in (0, 1)]
     try:
         path = str(tmp_path / "launch.json")
         res = autotune.tune_solver(sol, coll, cache_path=path, steps=3)
-        for k in (0, 1):
-            (b, x), timings = res[k]
-            assert len(timings) == 6 and min(timings.values()) == timings[(b, x)]
-            assert lbm.lbm_get_launch(k, 19, lbm.STORE_F32) == (b, x)
+        for k, n in ((0, 6), (1, 12)):
+            (b, x, c), timings = res[k]
+            assert len(timings) == n and min(timings.values()) == timings[(b, x, c)]
+            got = lbm.lbm_get_launch(k, 19, lbm.STORE_F32, full=True)
+            assert (got[0], got[1], got[3]) == (b, x, c)
         assert autotune.apply(path, 19, lbm.STORE_F32, dom.n_fluid) == 2
     finally:
-        for k, (b, x) in zip((0, 1), old):
-            lbm.lbm_set_launch(k, 19, lbm.STORE_F32, b, x)
+        for k, cfg in zip((0, 1), old):
+            lbm.lbm_set_launch(k, 19, lbm.STORE_F32, *cfg)
