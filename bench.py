@@ -283,9 +283,13 @@ def main():
         from paper_2408_06880_amd import server
         budget = 288 * (1 << 30) - 8 * (1 << 30)
         trace = server.make_trace(args.requests, 20.0, seed=31)
+        def retired(r):
+            log(f"request {r.rid} retired: {r.n_fluid} cells, {r.steps} steps, "
+                f"converged {r.converged}, latency {r.latency:.1f} s")
+
         res, met = server.Server(server.GpuStepper(storage=lbm.STORE_F16DEV), budget, K=100,
                                  tol=1e-6, max_steps=args.max_steps,
-                                 target_cells=args.target_cells).run(trace)
+                                 target_cells=args.target_cells, on_finish=retired).run(trace)
         work = sum(r.n_fluid * r.steps for r in res)
         capacity_s = work / (met["busy_mflups"] * 1e6) if met["busy_mflups"] else None
         print(json.dumps({

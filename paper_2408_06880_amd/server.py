@@ -83,11 +83,13 @@ def percentile(xs, p):
 
 class Server:
     def __init__(self, stepper, budget_bytes, K=100, tol=1e-6, max_steps=200_000,
-                 max_active=64, target_cells=None, clock=time.perf_counter, sleep=time.sleep):
+                 max_active=64, target_cells=None, clock=time.perf_counter, sleep=time.sleep,
+                 on_finish=None):
         """target_cells: admit new solves only while the active fluid cells
         stay below this (one solve is always admitted).  Enough cells to
         saturate the GPU keep throughput, fewer concurrent solves finish
-        sooner; None admits whatever the memory budget allows."""
+        sooner; None admits whatever the memory budget allows.  on_finish:
+        called with each Result as its request retires."""
         if K <= 0 or K % 2:
             raise ValueError("K must be a positive even number of steps")
         self.stepper = stepper
@@ -99,6 +101,7 @@ class Server:
         self.target_cells = target_cells
         self.clock = clock
         self.sleep = sleep
+        self.on_finish = on_finish
 
     def run(self, trace):
         """Serve `trace` (list of Request) in real time; returns (results,
@@ -176,6 +179,8 @@ class Server:
                     res.finished = self.clock() - t0
                     self.stepper.free(a["handle"])
                     used -= a["bytes"]
+                    if self.on_finish is not None:
+                        self.on_finish(res)
                 else:
                     keep.append(a)
             active = keep
