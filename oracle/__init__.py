@@ -31,7 +31,7 @@ _LIB_PATH = os.path.join(_HERE, "_liboracle.so")
 _lock = threading.Lock()
 _lib = None
 
-NONE, SRT, TRT, CUMULANT = 0, 1, 2, 3
+NONE, SRT, TRT, CUMULANT, MRT = 0, 1, 2, 3, 4
 BC_NOSLIP, BC_UBB, BC_PRESSURE = 0, 1, 2
 
 
@@ -54,6 +54,7 @@ class Params(ctypes.Structure):
         ("tau", ctypes.c_double),
         ("magic", ctypes.c_double),
         ("omega_bulk", ctypes.c_double),
+        ("rates", ctypes.c_double * 4),
         ("force", ctypes.c_double * 3),
         ("n_classes", ctypes.c_int32),
         ("cls_type", ctypes.c_int32 * 8),
@@ -62,15 +63,21 @@ class Params(ctypes.Structure):
     ]
 
 
+MRT_RATES = (1.4, 1.4, 1.2, 1.98)   # epsilon, pi, q, m (d'Humieres et al. 2002)
+
+
 def params(q=19, kind=SRT, tau=0.8, magic=3.0 / 16.0, omega_bulk=1.0, force=(0.0, 0.0, 0.0),
-           classes=()):
-    """classes: sequence of (type, (ux, uy, uz), rho) for labels 2, 3, ..."""
+           classes=(), rates=MRT_RATES):
+    """classes: sequence of (type, (ux, uy, uz), rho) for labels 2, 3, ...;
+    rates: MRT relaxation rates of the epsilon, pi, q and m moments."""
     p = Params()
     p.q = q
     p.kind = kind
     p.tau = tau
     p.magic = magic
     p.omega_bulk = omega_bulk
+    for a in range(4):
+        p.rates[a] = float(rates[a])
     for a in range(3):
         p.force[a] = float(force[a])
     p.n_classes = len(classes)
@@ -96,6 +103,7 @@ def _load():
         lib.orc_num_threads.restype = ctypes.c_int
         lib.orc_stencil_tables.argtypes = [i32, vp, vp, vp]
         lib.orc_collide_cells.argtypes = [P, i64, vp, vp]
+        lib.orc_mrt_matrix.argtypes = [vp]
         lib.orc_dense_step.argtypes = [P, vp, i32, i32, i32, u32, vp, vp]
         lib.orc_dense_run.argtypes = [P, vp, i32, i32, i32, u32, i64, vp, vp]
         lib.orc_dense_init.argtypes = [i32, vp, i64, ctypes.c_double, vp, vp]
@@ -144,6 +152,13 @@ def collide(p: Params, f: np.ndarray) -> np.ndarray:
     out = np.empty_like(f)
     _check(lib.orc_collide_cells(ctypes.byref(p), f.shape[0], _ptr(f), _ptr(out)), "collide")
     return out
+
+
+def mrt_matrix() -> np.ndarray:
+    """The D3Q19 MRT moment matrix M[k, i] (moment k of direction i)."""
+    M = np.empty((19, 19), np.float64)
+    _check(_load().orc_mrt_matrix(_ptr(M)), "mrt_matrix")
+    return M
 
 
 def _dims(labels):

@@ -102,15 +102,16 @@ int orc_num_threads(void) { return omp_get_max_threads(); }
 /* Parameters.                                                          */
 /* ------------------------------------------------------------------ */
 
-enum { ORC_NONE = 0, ORC_SRT = 1, ORC_TRT = 2, ORC_CUMULANT = 3 };
+enum { ORC_NONE = 0, ORC_SRT = 1, ORC_TRT = 2, ORC_CUMULANT = 3, ORC_MRT = 4 };
 enum { ORC_BC_NOSLIP = 0, ORC_BC_UBB = 1, ORC_BC_PRESSURE = 2 };
 
 typedef struct {
   int32_t q;
-  int32_t kind;         /* ORC_NONE / SRT / TRT / CUMULANT                  */
+  int32_t kind;         /* ORC_NONE / SRT / TRT / CUMULANT / MRT            */
   double tau;           /* relaxation time, nu = (tau - 1/2)/3              */
   double magic;         /* TRT magic parameter Lambda                       */
-  double omega_bulk;    /* cumulant trace (bulk) rate                       */
+  double omega_bulk;    /* cumulant trace / MRT energy (bulk) rate          */
+  double rates[4];      /* MRT rates of epsilon, pi, q, m moments           */
   double force[3];      /* constant body force density F                    */
   int32_t n_classes;    /* boundary classes for labels >= 2                 */
   int32_t cls_type[8];  /* ORC_BC_*                                         */
@@ -314,12 +315,97 @@ static void orc_collide_cumulant(const orc_stencil* s, const orc_params* P, cons
       }
 }
 
+/* Multiple-relaxation-time operator for D3Q19 (the paper lists MRT with
+ * the classical operators, Section "Lattice Boltzmann Method"; moment basis
+ * of d'Humieres et al. 2002).  The 19 moments are the polynomials below in
+ * the lattice velocity; they are mutually orthogonal over the D3Q19 set, so
+ * M^-1 = M^T diag(1 / |row|^2).  Every moment relaxes toward the moment of
+ * the same second-order equilibrium the SRT/TRT operators use, with its own
+ * rate; Guo's source enters in moment space with weight (1 - s/2).
+ * Rates: density and momentum are conserved (rate irrelevant, 1 used);
+ * energy e: omega_bulk; epsilon: rates[0]; the shear moments 3p_xx, p_ww,
+ * p_xy, p_yz, p_xz: 1/tau; pi_xx, pi_ww: rates[1]; energy flux q:
+ * rates[2]; third-order m: rates[3]. */
+static double orc_mrt_poly(int k, const int c[3]) {
+  double x = c[0], y = c[1], z = c[2], c2 = x * x + y * y + z * z;
+  switch (k) {
+    case 0: return 1.0;
+    case 1: return 19.0 * c2 - 30.0;
+    case 2: return (21.0 * c2 * c2 - 53.0 * c2 + 24.0) / 2.0;
+    case 3: return x;
+    case 4: return (5.0 * c2 - 9.0) * x;
+    case 5: return y;
+    case 6: return (5.0 * c2 - 9.0) * y;
+    case 7: return z;
+    case 8: return (5.0 * c2 - 9.0) * z;
+    case 9: return 3.0 * x * x - c2;
+    case 10: return (3.0 * c2 - 5.0) * (3.0 * x * x - c2);
+    case 11: return y * y - z * z;
+    case 12: return (3.0 * c2 - 5.0) * (y * y - z * z);
+    case 13: return x * y;
+    case 14: return y * z;
+    case 15: return x * z;
+    case 16: return (y * y - z * z) * x;
+    case 17: return (z * z - x * x) * y;
+    default: return (x * x - y * y) * z;
+  }
+}
+
+static double orc_mrt_rate(const orc_params* P, int k) {
+  switch (k) {
+    case 0: case 3: case 5: case 7: return 1.0;
+    case 1: return P->omega_bulk;
+    case 2: return P->rates[0];
+    case 9: case 11: case 13: case 14: case 15: return 1.0 / P->tau;
+    case 10: case 12: return P->rates[1];
+    case 4: case 6: case 8: return P->rates[2];
+    default: return P->rates[3];
+  }
+}
+
+static void orc_collide_mrt(const orc_stencil* s, const orc_params* P, const double* f,
+                            double* out) {
+  double rho, u[3];
+  orc_macros(s, f, P->force, &rho, u);
+  double mstar[19];
+  for (int k = 0; k < 19; ++k) {
+    double m = 0.0, meq = 0.0, ms = 0.0;
+    for (int i = 0; i < 19; ++i) {
+      double pk = orc_mrt_poly(k, s->c[i]);
+      m += pk * f[i];
+      meq += pk * orc_feq(s, i, rho, u);
+      ms += pk * orc_guo(s, i, u, P->force);
+    }
+    double sk = orc_mrt_rate(P, k);
+    mstar[k] = m - sk * (m - meq) + (1.0 - 0.5 * sk) * ms;
+  }
+  for (int i = 0; i < 19; ++i) {
+    double acc = 0.0;
+    for (int k = 0; k < 19; ++k) {
+      double norm = 0.0;
+      for (int j = 0; j < 19; ++j) norm += orc_mrt_poly(k, s->c[j]) * orc_mrt_poly(k, s->c[j]);
+      acc += orc_mrt_poly(k, s->c[i]) * mstar[k] / norm;
+    }
+    out[i] = acc;
+  }
+}
+
+/* Moment matrix of the MRT basis (row k, column i) for tests. */
+int orc_mrt_matrix(double* M) {
+  orc_stencil s;
+  if (orc_stencil_init(&s, 19)) return -1;
+  for (int k = 0; k < 19; ++k)
+    for (int i = 0; i < 19; ++i) M[k * 19 + i] = orc_mrt_poly(k, s.c[i]);
+  return 0;
+}
+
 static void orc_collide(const orc_stencil* s, const orc_params* P, const double* f,
                         double* out) {
   switch (P->kind) {
     case ORC_SRT: orc_collide_srt(s, P, f, out); break;
     case ORC_TRT: orc_collide_trt(s, P, f, out); break;
     case ORC_CUMULANT: orc_collide_cumulant(s, P, f, out); break;
+    case ORC_MRT: orc_collide_mrt(s, P, f, out); break;
     default:
       for (int i = 0; i < s->q; ++i) out[i] = f[i];
   }
@@ -330,6 +416,7 @@ int orc_collide_cells(const orc_params* P, int64_t n, const double* f_in, double
   orc_stencil s;
   if (orc_stencil_init(&s, P->q)) return -1;
   if (P->kind == ORC_CUMULANT && P->q != 27) return -1;
+  if (P->kind == ORC_MRT && P->q != 19) return -1;
   for (int64_t k = 0; k < n; ++k) orc_collide(&s, P, f_in + k * s.q, f_out + k * s.q);
   return 0;
 }
@@ -385,6 +472,7 @@ int orc_dense_step(const orc_params* P, const uint8_t* labels, int nx, int ny, i
   orc_stencil s;
   if (orc_stencil_init(&s, P->q)) return -1;
   if (P->kind == ORC_CUMULANT && P->q != 27) return -1;
+  if (P->kind == ORC_MRT && P->q != 19) return -1;
   const int64_t N = (int64_t)nx * ny * nz;
   const int q = s.q;
 #pragma omp parallel for schedule(static)
@@ -650,6 +738,7 @@ int orc_sparse_step(const orc_params* P, int64_t n_fluid, int64_t S, const int32
   orc_stencil s;
   if (orc_stencil_init(&s, P->q)) return -1;
   if (P->kind == ORC_CUMULANT && P->q != 27) return -1;
+  if (P->kind == ORC_MRT && P->q != 19) return -1;
   const int q = s.q;
   orc_sparse_links(&s, P, n_links, links, pdf);
   if ((t & 1) == 0) {

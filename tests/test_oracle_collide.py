@@ -82,7 +82,7 @@ def _random_states(q, n, seed, amp=1e-2):
 
 
 KINDS = [(19, oracle.SRT), (19, oracle.TRT), (27, oracle.SRT), (27, oracle.TRT),
-         (27, oracle.CUMULANT)]
+         (27, oracle.CUMULANT), (19, oracle.MRT)]
 
 
 @pytest.mark.parametrize("q,kind", KINDS)
@@ -266,3 +266,67 @@ def test_none_is_identity():
 def test_cumulant_rejects_d3q19():
     with pytest.raises(RuntimeError):
         oracle.collide(oracle.params(q=19, kind=oracle.CUMULANT), _random_states(19, 1, 0))
+
+
+# ------------------------------------------------------------------- MRT
+def test_mrt_basis_orthogonal_with_published_norms():
+    """The D3Q19 moment basis of d'Humieres et al. (2002) is orthogonal over
+    the lattice; M M^T is diagonal with the norms published there.  Rows are
+    either even or odd under c -> -c, so the basis splits the populations
+    into the symmetric and antisymmetric halves TRT works with."""
+    M = oracle.mrt_matrix()
+    G = M @ M.T
+    assert np.array_equal(G, np.diag(np.diag(G)))
+    assert np.diag(G).tolist() == [19, 2394, 252, 10, 40, 10, 40, 10, 40, 36, 72, 12, 24,
+                                   4, 4, 4, 8, 8, 8]
+    _, _, opp = oracle.stencil(19)
+    odd = {3, 4, 5, 6, 7, 8, 16, 17, 18}
+    for k in range(19):
+        sign = -1 if k in odd else 1
+        assert np.array_equal(M[k, opp], sign * M[k])
+    # the conserved rows are density and momentum
+    c, _, _ = oracle.stencil(19)
+    assert np.array_equal(M[0], np.ones(19))
+    assert np.array_equal(M[[3, 5, 7]], c.T)
+
+
+def test_mrt_reduces_to_trt_and_srt():
+    """Even moments at omega+, odd ones at omega- is TRT (any magic);
+    every rate at 1/tau is SRT."""
+    tau, magic = 0.77, 0.21
+    F = (2e-4, -1e-4, 5e-5)
+    omp, omm = 1 / tau, 1 / (0.5 + magic / (tau - 0.5))
+    f = _random_states(19, 40, seed=11)
+    mrt = oracle.collide(oracle.params(19, oracle.MRT, tau=tau, omega_bulk=omp, force=F,
+                                       rates=(omp, omp, omm, omm)), f)
+    trt = oracle.collide(oracle.params(19, oracle.TRT, tau=tau, magic=magic, force=F), f)
+    assert np.max(np.abs(mrt - trt)) < 1e-15
+    mrt = oracle.collide(oracle.params(19, oracle.MRT, tau=tau, omega_bulk=omp, force=F,
+                                       rates=(omp,) * 4), f)
+    srt = oracle.collide(oracle.params(19, oracle.SRT, tau=tau, force=F), f)
+    assert np.max(np.abs(mrt - srt)) < 1e-15
+
+
+def test_mrt_relaxes_each_moment_group_at_its_rate():
+    """Unforced: the non-equilibrium part of moment k is multiplied by
+    (1 - s_k), with s_k the rate of its group; conserved moments keep their
+    values."""
+    tau, wb, rates = 0.9, 1.19, (1.4, 1.1, 1.2, 1.98)
+    rate = {1: wb, 2: rates[0], 10: rates[1], 12: rates[1], 4: rates[2], 6: rates[2],
+            8: rates[2], 16: rates[3], 17: rates[3], 18: rates[3]}
+    for k in (9, 11, 13, 14, 15):
+        rate[k] = 1 / tau
+    M = oracle.mrt_matrix()
+    c, _, _ = oracle.stencil(19)
+    f = _random_states(19, 20, seed=2)
+    fs = oracle.collide(oracle.params(19, oracle.MRT, tau=tau, omega_bulk=wb, rates=rates), f)
+    for n in range(f.shape[0]):
+        rho = f[n].sum()
+        u = f[n] @ c / rho
+        meq = M @ _feq(19, rho, u)
+        m, ms = M @ f[n], M @ fs[n]
+        for k in range(19):
+            if k in (0, 3, 5, 7):
+                assert abs(ms[k] - m[k]) < 1e-15
+            else:
+                assert abs((ms[k] - meq[k]) - (1 - rate[k]) * (m[k] - meq[k])) < 1e-14
