@@ -254,6 +254,8 @@ def main():
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--pipelined", type=int, default=0, choices=[0, 1],
                     help="odd kernel as persistent workgroups prefetching the next tile")
+    ap.add_argument("--coll", default="trt", choices=["trt", "srt", "mrt"],
+                    help="packing workload: collision operator (D3Q19)")
     ap.add_argument("--even-cells", type=int, default=0, choices=[0, 1, 2],
                     help="cells per thread of the even-step kernel (0: the library's "
                          "default, two for 16-bit storage)")
@@ -366,7 +368,8 @@ def main():
     if vessel:
         coll = lbm.collision(lbm.COLL_CUMULANT, tau=0.8, omega_bulk=1.0, force=force)
     else:
-        coll = lbm.collision(lbm.COLL_TRT, tau=args.tau, magic=magic, force=force)
+        kind = {"trt": lbm.COLL_TRT, "srt": lbm.COLL_SRT, "mrt": lbm.COLL_MRT}[args.coll]
+        coll = lbm.collision(kind, tau=args.tau, magic=magic, force=force, omega_bulk=1.19)
     sol.init()
     sol.step(args.warmup, coll, bs)
     torch.cuda.synchronize()
@@ -462,7 +465,7 @@ def main():
         log(f"cpu oracle {cpu['value']:.1f} MFLUPS on {cpu['cores']} threads")
 
     achieved = nf * b_odd / t_odd / 1e9
-    workload = (f"sparse D3Q19 TRT AA, {args.L}^3 periodic overlapping-sphere packing "
+    workload = (f"sparse D3Q19 {args.coll.upper()} AA, {args.L}^3 periodic overlapping-sphere packing "
                 f"phi={info['phi']:.3f} (r 4-12, seed {info['seed']})")
     if vessel:
         workload = (f"sparse D3Q27 cumulant AA (tau 0.8), {args.L}^3 vessel tree "

@@ -61,7 +61,8 @@ typedef int32_t lbm_status;
 #define LBM_ESTATE (-6)    /* layout / parity / storage mismatch between inputs   */
 
 enum { LBM_D3Q19 = 19, LBM_D3Q27 = 27 };
-enum { LBM_COLL_NONE = 0, LBM_COLL_SRT = 1, LBM_COLL_TRT = 2, LBM_COLL_CUMULANT = 3 };
+enum { LBM_COLL_NONE = 0, LBM_COLL_SRT = 1, LBM_COLL_TRT = 2, LBM_COLL_CUMULANT = 3,
+       LBM_COLL_MRT = 4 };
 /* Storage of the PDF-list.  *DEV formats store the deviation f_i - w_i
  * from the rest weights ("zero-centred" storage option, Section "Code
  * Generation for Sparse Kernels"), 16-bit ones scaled by 2^dev_exp.  All
@@ -159,6 +160,13 @@ typedef struct {
  *            omega- from magic = (1/omega+ - 1/2)(1/omega- - 1/2).
  *  CUMULANT: D3Q27 only; second-order shear/deviatoric moments relax with
  *            1/tau, the trace with omega_bulk, all higher cumulants -> 0.
+ *  MRT:      D3Q19 only; the 19 orthogonal moments of d'Humieres et al.
+ *            (2002) relax toward the moments of the same second-order
+ *            equilibrium: shear moments (3p_xx, p_ww, p_xy, p_yz, p_xz)
+ *            with 1/tau, energy e with omega_bulk, epsilon, pi_xx/pi_ww,
+ *            energy flux q and third-order m with rates[0..3] (each in
+ *            (0, 2)); the Guo source enters every moment with (1 - s/2).
+ *            Even rates = 1/tau and odd rates = omega- give TRT exactly.
  *  force:    constant body force density (Guo scheme, half-force velocity).
  */
 typedef struct {
@@ -166,8 +174,9 @@ typedef struct {
   int32_t reserved;
   double tau;
   double magic;          /* TRT Lambda, e.g. 3/16                               */
-  double omega_bulk;     /* cumulant trace rate, e.g. 1                         */
+  double omega_bulk;     /* cumulant trace rate, MRT energy rate, e.g. 1       */
   double force[3];
+  double rates[4];       /* MRT only: rates of the epsilon, pi, q, m moments    */
 } lbm_collision;
 
 /* Boundary classes for labels 2..9.  UBB: moving wall u (bounce-back plus

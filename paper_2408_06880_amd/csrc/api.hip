@@ -101,7 +101,7 @@ lbm_status check_state(const lbm_state* s) {
 
 lbm_status check_coll(const lbm_collision* c, int q) {
   if (!c) return fail(LBM_EINVAL, "collision is NULL");
-  if (c->kind < LBM_COLL_NONE || c->kind > LBM_COLL_CUMULANT)
+  if (c->kind < LBM_COLL_NONE || c->kind > LBM_COLL_MRT)
     return fail(LBM_EINVAL, "unknown collision kind %d", c->kind);
   if (c->kind != LBM_COLL_NONE && !(c->tau > 0.5))
     return fail(LBM_EINVAL, "tau must be > 1/2 (got %g)", c->tau);
@@ -109,21 +109,29 @@ lbm_status check_coll(const lbm_collision* c, int q) {
     return fail(LBM_EINVAL, "TRT magic parameter must be > 0 (got %g)", c->magic);
   if (c->kind == LBM_COLL_CUMULANT && q != 27)
     return fail(LBM_EINVAL, "the cumulant operator needs D3Q27");
-  if (c->kind == LBM_COLL_CUMULANT && !(c->omega_bulk > 0.0 && c->omega_bulk < 2.0))
+  if ((c->kind == LBM_COLL_CUMULANT || c->kind == LBM_COLL_MRT) &&
+      !(c->omega_bulk > 0.0 && c->omega_bulk < 2.0))
     return fail(LBM_EINVAL, "omega_bulk must be in (0, 2) (got %g)", c->omega_bulk);
+  if (c->kind == LBM_COLL_MRT && q != 19)
+    return fail(LBM_EINVAL, "the MRT operator needs D3Q19");
+  if (c->kind == LBM_COLL_MRT)
+    for (int a = 0; a < 4; ++a)
+      if (!(c->rates[a] > 0.0 && c->rates[a] < 2.0))
+        return fail(LBM_EINVAL, "MRT rates must be in (0, 2) (rates[%d] = %g)", a, c->rates[a]);
   for (int a = 0; a < 3; ++a)
     if (!isfinite(c->force[a])) return fail(LBM_EINVAL, "force must be finite");
   return LBM_OK;
 }
 
-void coll_rates(const lbm_collision* c, double& om1, double& om2) {
+void coll_rates(const lbm_collision* c, double& om1, double& om2, double* rates) {
   om1 = om2 = 0.0;
+  for (int a = 0; a < 4; ++a) rates[a] = c->kind == LBM_COLL_MRT ? c->rates[a] : 0.0;
   if (c->kind == LBM_COLL_SRT) {
     om1 = om2 = 1.0 / c->tau;
   } else if (c->kind == LBM_COLL_TRT) {
     om1 = 1.0 / c->tau;
     om2 = 1.0 / (0.5 + c->magic / (c->tau - 0.5));
-  } else if (c->kind == LBM_COLL_CUMULANT) {
+  } else if (c->kind == LBM_COLL_CUMULANT || c->kind == LBM_COLL_MRT) {
     om1 = 1.0 / c->tau;
     om2 = c->omega_bulk;
   }
@@ -212,7 +220,7 @@ Seg make_seg(const lbm_state* s, const lbm_collision* c) {
     g.rval = r.val;
   }
   if (c) {
-    coll_rates(c, g.om1, g.om2);
+    coll_rates(c, g.om1, g.om2, g.rates);
     for (int a = 0; a < 3; ++a) g.F[a] = c->force[a];
   }
   const int e = is16(s->storage) ? s->dev_exp : 0;
@@ -259,7 +267,7 @@ uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); 
 
 extern "C" {
 
-int32_t lbm_abi_version(void) { return 2; }
+int32_t lbm_abi_version(void) { return 3; }
 
 const char* lbm_last_error(void) { return g_err.c_str(); }
 
@@ -709,7 +717,7 @@ lbm_status lbm_dense_step(lbm_dense_state* s, int32_t n_steps, const lbm_collisi
   a.N = (uint32_t)((int64_t)s->nx * s->ny * s->nz);
   a.xcd_remap = cfg.xcd_remap;
   a.ntiles = ceil_div(a.N, (uint64_t)cfg.block);
-  coll_rates(c, a.om1, a.om2);
+  coll_rates(c, a.om1, a.om2, a.rates);
   for (int k = 0; k < 3; ++k) a.F[k] = c->force[k];
   const int e = is16(s->storage) ? s->dev_exp : 0;
   a.scale = ldexpf(1.0f, e);

@@ -15,12 +15,13 @@
 
 namespace lbm {
 
-enum CollKind { COLL_NONE = 0, COLL_SRT = 1, COLL_TRT = 2, COLL_CUMULANT = 3 };
+enum CollKind { COLL_NONE = 0, COLL_SRT = 1, COLL_TRT = 2, COLL_CUMULANT = 3, COLL_MRT = 4 };
 
 template <class R>
 struct CollParams {
-  R om1, om2;  // SRT: omega; TRT: omega+, omega-; cumulant: shear, bulk
+  R om1, om2;  // SRT: omega; TRT: omega+, omega-; cumulant, MRT: shear, bulk
   R Fx, Fy, Fz;
+  R r[4];      // MRT: epsilon, pi, q, m rates
 };
 
 template <int Q, class R>

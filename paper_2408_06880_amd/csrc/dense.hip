@@ -58,6 +58,7 @@ __global__ __launch_bounds__(256) void k_dense_step(const DenseArgs a) {
   CollParams<R> p;
   p.om1 = R(a.om1);
   p.om2 = R(a.om2);
+  for (int r = 0; r < 4; ++r) p.r[r] = R(a.rates[r]);
   p.Fx = R(a.F[0]);
   p.Fy = R(a.F[1]);
   p.Fz = R(a.F[2]);
@@ -134,6 +135,7 @@ hipError_t launch_dense_step(int q, int coll, int storage, bool odd, const Dense
     if (coll == COLL_SRT) return launch_dense_qc<19, COLL_SRT>(storage, odd, a, block, st);
     if (coll == COLL_TRT) return launch_dense_qc<19, COLL_TRT>(storage, odd, a, block, st);
     if (coll == COLL_NONE) return launch_dense_qc<19, COLL_NONE>(storage, odd, a, block, st);
+    if (coll == COLL_MRT) return launch_dense_qc<19, COLL_MRT>(storage, odd, a, block, st);
   } else if (q == 27) {
     if (coll == COLL_SRT) return launch_dense_qc<27, COLL_SRT>(storage, odd, a, block, st);
     if (coll == COLL_TRT) return launch_dense_qc<27, COLL_TRT>(storage, odd, a, block, st);

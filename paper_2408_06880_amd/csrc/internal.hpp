@@ -94,6 +94,7 @@ struct DenseArgs {
   uint32_t ntiles;
   int32_t pad;
   double om1, om2, F[3];
+  double rates[4];
   float scale, inv_scale;
 };
 hipError_t launch_dense_mask(const uint8_t* labels, int nx, int ny, int nz, uint32_t periodic,

@@ -137,6 +137,7 @@ struct Seg {
   double om1;            // SRT omega / TRT omega+ / cumulant shear rate
   double om2;            // TRT omega- / cumulant bulk rate
   double F[3];           // body force
+  double rates[4];       // MRT epsilon, pi, q, m rates
   float scale;           // 2^dev_exp (16-bit storage)
   float inv_scale;       // 2^-dev_exp
 };

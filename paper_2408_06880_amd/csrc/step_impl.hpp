@@ -23,6 +23,7 @@
 #pragma once
 
 #include "cumulant.hpp"
+#include "mrt.hpp"
 
 namespace lbm {
 
@@ -35,6 +36,9 @@ __device__ __forceinline__ void collide(R (&d)[Q], const CollParams<R>& p) {
   } else if constexpr (COLL == COLL_CUMULANT) {
     static_assert(Q == 27, "cumulant needs D3Q27");
     collide_cumulant<R>(d, p);
+  } else if constexpr (COLL == COLL_MRT) {
+    static_assert(Q == 19, "MRT is defined for D3Q19");
+    collide_mrt<R>(d, p);
   }
 }
 
@@ -46,6 +50,7 @@ __device__ __forceinline__ CollParams<R> seg_params(const Seg& g) {
   p.Fx = R(g.F[0]);
   p.Fy = R(g.F[1]);
   p.Fz = R(g.F[2]);
+  for (int a = 0; a < 4; ++a) p.r[a] = R(g.rates[a]);
   return p;
 }
 

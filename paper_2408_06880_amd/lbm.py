@@ -25,7 +25,9 @@ LIB_PATH = os.environ.get("LBM_LIBRARY") or os.path.join(_PKG, "liblbm.so")
 LBM_OK, LBM_EINVAL, LBM_ERANGE, LBM_ENOMEM = 0, -1, -2, -3
 LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = -4, -5, -6
 D3Q19, D3Q27 = 19, 27
-COLL_NONE, COLL_SRT, COLL_TRT, COLL_CUMULANT = 0, 1, 2, 3
+COLL_NONE, COLL_SRT, COLL_TRT, COLL_CUMULANT, COLL_MRT = 0, 1, 2, 3, 4
+# MRT rates of the epsilon, pi, q and m moments suggested by d'Humieres et al. (2002)
+MRT_RATES = (1.4, 1.4, 1.2, 1.98)
 STORE_F64, STORE_F32, STORE_F16DEV, STORE_BF16DEV, STORE_F32DEV = 0, 1, 2, 3, 4
 ORDER_MORTON, ORDER_LEX, ORDER_BLOCKED = 0, 1, 2
 BC_NOSLIP, BC_UBB, BC_PRESSURE = 0, 1, 2
@@ -53,7 +55,7 @@ class lbm_state(ctypes.Structure):
 
 class lbm_collision(ctypes.Structure):
     _fields_ = [("kind", _i32), ("reserved", _i32), ("tau", _f64), ("magic", _f64),
-                ("omega_bulk", _f64), ("force", _f64 * 3)]
+                ("omega_bulk", _f64), ("force", _f64 * 3), ("rates", _f64 * 4)]
 
 
 class lbm_bclass(ctypes.Structure):
@@ -322,11 +324,15 @@ def lbm_copy(dst, src, nbytes, stream=None):
 
 
 # ------------------------------------------------------- conveniences
-def collision(kind=COLL_TRT, tau=0.8, magic=3.0 / 16.0, omega_bulk=1.0, force=(0.0, 0.0, 0.0)):
+def collision(kind=COLL_TRT, tau=0.8, magic=3.0 / 16.0, omega_bulk=1.0, force=(0.0, 0.0, 0.0),
+              rates=MRT_RATES):
+    """rates: MRT only (epsilon, pi, q, m groups)."""
     c = lbm_collision()
     c.kind, c.tau, c.magic, c.omega_bulk = kind, tau, magic, omega_bulk
     for a in range(3):
         c.force[a] = float(force[a])
+    for a in range(4):
+        c.rates[a] = float(rates[a])
     return c
 
 

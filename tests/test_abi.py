@@ -27,13 +27,13 @@ def test_library_exports_every_declared_symbol():
     lib = lbm.load()
     for name in declared_functions():
         assert hasattr(lib, name), name
-    assert lbm.lbm_abi_version() == 2
+    assert lbm.lbm_abi_version() == 3
 
 
 def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(lbm.lbm_layout) == 56
     assert ctypes.sizeof(lbm.lbm_state) == 56 + 8 + 40 + 8
-    assert ctypes.sizeof(lbm.lbm_collision) == 8 + 8 * 6
+    assert ctypes.sizeof(lbm.lbm_collision) == 8 + 8 * 6 + 8 * 4
     assert ctypes.sizeof(lbm.lbm_bspec) == 8 + 8 * 40
     assert ctypes.sizeof(lbm.lbm_reduction) == 48
     assert ctypes.sizeof(lbm.lbm_dense_state) == 32 + 16 + 8
@@ -79,6 +79,13 @@ def test_invalid_arguments_rejected_on_host():
     expect(lbm.LBM_EINVAL, lbm.lbm_step, _fake_state(q=19), 1,
            lbm.collision(lbm.COLL_CUMULANT, tau=0.8), None, 0)
     expect(lbm.LBM_EINVAL, lbm.lbm_step, _fake_state(storage=9), 1, lbm.collision(), None, 0)
+    # MRT: D3Q19 only, every rate in (0, 2)
+    expect(lbm.LBM_EINVAL, lbm.lbm_step, _fake_state(q=27), 1,
+           lbm.collision(lbm.COLL_MRT, tau=0.8), None, 0)
+    expect(lbm.LBM_EINVAL, lbm.lbm_step, _fake_state(), 1,
+           lbm.collision(lbm.COLL_MRT, tau=0.8, rates=(1.4, 1.4, 2.0, 1.0)), None, 0)
+    expect(lbm.LBM_EINVAL, lbm.lbm_step, _fake_state(), 1,
+           lbm.collision(lbm.COLL_MRT, tau=0.8, omega_bulk=0.0), None, 0)
     st = _fake_state(storage=lbm.STORE_F16DEV)
     st.dev_exp = 30
     expect(lbm.LBM_EINVAL, lbm.lbm_step, st, 1, lbm.collision(), None, 0)

@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 from paper_2408_06880_amd import lbm  # noqa: E402
 
 KIND = {lbm.COLL_NONE: oracle.NONE, lbm.COLL_SRT: oracle.SRT, lbm.COLL_TRT: oracle.TRT,
-        lbm.COLL_CUMULANT: oracle.CUMULANT}
+        lbm.COLL_CUMULANT: oracle.CUMULANT, lbm.COLL_MRT: oracle.MRT}
 BC = {lbm.BC_NOSLIP: oracle.BC_NOSLIP, lbm.BC_UBB: oracle.BC_UBB,
       lbm.BC_PRESSURE: oracle.BC_PRESSURE}
 
@@ -42,11 +42,14 @@ def _check_index(dom):
         assert ln[0::2].min() >= 0 and ln[0::2].max() < q * S
 
 
-def _params(q, kind, tau, force, classes, magic=3.0 / 16.0, omega_bulk=1.0):
-    coll = lbm.collision(kind, tau=tau, magic=magic, omega_bulk=omega_bulk, force=force)
+def _params(q, kind, tau, force, classes, magic=3.0 / 16.0, omega_bulk=1.0,
+            rates=(1.3, 1.5, 1.2, 1.7)):
+    coll = lbm.collision(kind, tau=tau, magic=magic, omega_bulk=omega_bulk, force=force,
+                         rates=rates)
     bs = lbm.bspec(classes)
     op = oracle.params(q=q, kind=KIND[kind], tau=tau, magic=magic, omega_bulk=omega_bulk,
-                       force=force, classes=[(BC[t], u, r) for t, u, r in classes])
+                       force=force, classes=[(BC[t], u, r) for t, u, r in classes],
+                       rates=rates)
     return coll, bs, op
 
 
@@ -164,6 +167,8 @@ AA_CASES = [
     (19, lbm.COLL_SRT, lbm.STORE_F32), (19, lbm.COLL_TRT, lbm.STORE_F32),
     (19, lbm.COLL_TRT, lbm.STORE_F32DEV), (27, lbm.COLL_CUMULANT, lbm.STORE_F32),
     (27, lbm.COLL_CUMULANT, lbm.STORE_F32DEV), (27, lbm.COLL_TRT, lbm.STORE_F32),
+    (19, lbm.COLL_MRT, lbm.STORE_F64), (19, lbm.COLL_MRT, lbm.STORE_F32),
+    (19, lbm.COLL_MRT, lbm.STORE_F32DEV),
 ]
 
 
@@ -202,7 +207,7 @@ def test_aa_steps_match_oracle(q, kind, storage):
 
 
 @pytest.mark.parametrize("q,kind", [(19, lbm.COLL_TRT), (19, lbm.COLL_SRT),
-                                    (27, lbm.COLL_CUMULANT)])
+                                    (27, lbm.COLL_CUMULANT), (19, lbm.COLL_MRT)])
 @pytest.mark.parametrize("storage,dev_exp", [(lbm.STORE_F16DEV, 14), (lbm.STORE_F16DEV, 10),
                                              (lbm.STORE_BF16DEV, 0)])
 def test_16bit_one_step_bounds(q, kind, storage, dev_exp):
@@ -365,12 +370,14 @@ def test_batch_is_bitwise_identical_to_alone():
 
 
 # ------------------------------------------------------------ dense
-@pytest.mark.parametrize("storage", [lbm.STORE_F64, lbm.STORE_F32])
-def test_dense_comparator_matches_oracle(storage):
+@pytest.mark.parametrize("storage,kind", [(lbm.STORE_F64, lbm.COLL_TRT),
+                                          (lbm.STORE_F32, lbm.COLL_TRT),
+                                          (lbm.STORE_F64, lbm.COLL_MRT)])
+def test_dense_comparator_matches_oracle(storage, kind):
     lab = inputs.random_mask((15, 14, 13), 0.35, seed=8)
     per = 6
     q = 19
-    coll, _, op = _params(q, lbm.COLL_TRT, 0.8, (1e-5, 0, 0), [])
+    coll, _, op = _params(q, kind, 0.8, (1e-5, 0, 0), [])
     ds = lbm.DenseSolver(lab, per, q, storage)
     ds.init()
     ds.step(20, coll)
@@ -679,13 +686,14 @@ def test_runs_full_size_packing(packing256, order):
 
 
 # ------------------------------------------------------------ pull scheme
-@pytest.mark.parametrize("compact", [False, True])
-def test_pull_scheme_bitwise_equals_aa(compact):
+@pytest.mark.parametrize("compact,kind", [(False, lbm.COLL_TRT), (True, lbm.COLL_TRT),
+                                          (False, lbm.COLL_MRT)])
+def test_pull_scheme_bitwise_equals_aa(compact, kind):
     """An AA odd+even pair performs the same collisions on the same inputs
     as two pull steps (Section "In-place Streaming: AA Pattern"), so after
     every even step count the two schemes agree bit for bit (links too)."""
     lab = inputs.random_mask((22, 19, 17), 0.3, seed=6, n_classes=3, class_fraction=0.5)
-    coll, bs, op = _params(19, lbm.COLL_TRT, 0.75, (1e-5, 0, 0), CLASSES)
+    coll, bs, op = _params(19, kind, 0.75, (1e-5, 0, 0), CLASSES)
     doms = [lbm.SparseDomain(lab, 5, 19, lbm.ORDER_BLOCKED) for _ in range(2)]
     if compact:
         for d in doms:

@@ -48,16 +48,19 @@ def _states(q, n, seed):
 
 CASES = [(19, 1, 0.8, 0.0, 1.0), (19, 2, 0.7, 3 / 16, 1.0), (27, 1, 0.9, 0.0, 1.0),
          (27, 2, 0.6, 3 / 16, 1.0), (27, 3, 0.62, 0.0, 1.0), (27, 3, 0.8, 0.0, 1.3),
-         (27, 3, 1.0, 0.0, 1.0)]
+         (27, 3, 1.0, 0.0, 1.0), (19, 4, 0.8, 0.0, 1.19), (19, 4, 0.55, 0.0, 1.6)]
+MRT_RATES = {0.8: (1.4, 1.4, 1.2, 1.98), 0.55: (1.1, 1.7, 0.6, 1.3)}
 
 
 @pytest.mark.parametrize("q,kind,tau,magic,wb", CASES)
 def test_device_collision_matches_oracle(hostlib, q, kind, tau, magic, wb):
     F = (1e-5, -2e-6, 3e-6)
-    p = oracle.params(q=q, kind=kind, tau=tau, magic=magic, omega_bulk=wb, force=F)
+    rates = MRT_RATES.get(tau, oracle.MRT_RATES) if kind == 4 else oracle.MRT_RATES
+    p = oracle.params(q=q, kind=kind, tau=tau, magic=magic, omega_bulk=wb, force=F,
+                      rates=rates)
     om1 = 1 / tau
     om2 = om1 if kind == 1 else (1 / (0.5 + magic / (tau - 0.5)) if kind == 2 else wb)
-    P = np.array((om1, om2) + F)
+    P = np.array((om1, om2) + F + tuple(rates))
     f = _states(q, 200, seed=q + kind)
     ref = oracle.collide(p, f)
     _, w, _ = oracle.stencil(q)
