@@ -31,7 +31,7 @@ _LIB_PATH = os.path.join(_HERE, "_liboracle.so")
 _lock = threading.Lock()
 _lib = None
 
-NONE, SRT, TRT, CUMULANT, MRT = 0, 1, 2, 3, 4
+NONE, SRT, TRT, CUMULANT, MRT, CM = 0, 1, 2, 3, 4, 5
 BC_NOSLIP, BC_UBB, BC_PRESSURE = 0, 1, 2
 
 
@@ -64,12 +64,16 @@ class Params(ctypes.Structure):
 
 
 MRT_RATES = (1.4, 1.4, 1.2, 1.98)   # epsilon, pi, q, m (d'Humieres et al. 2002)
+CM_RATES = (1.0, 1.0, 1.0, 1.0)     # central moments of order 3, 4, 5, 6
 
 
 def params(q=19, kind=SRT, tau=0.8, magic=3.0 / 16.0, omega_bulk=1.0, force=(0.0, 0.0, 0.0),
-           classes=(), rates=MRT_RATES):
+           classes=(), rates=None):
     """classes: sequence of (type, (ux, uy, uz), rho) for labels 2, 3, ...;
-    rates: MRT relaxation rates of the epsilon, pi, q and m moments."""
+    rates: MRT relaxation rates of the epsilon, pi, q and m moments, or
+    central-moment rates of orders 3-6 (default per kind)."""
+    if rates is None:
+        rates = CM_RATES if kind == CM else MRT_RATES
     p = Params()
     p.q = q
     p.kind = kind

@@ -102,7 +102,7 @@ int orc_num_threads(void) { return omp_get_max_threads(); }
 /* Parameters.                                                          */
 /* ------------------------------------------------------------------ */
 
-enum { ORC_NONE = 0, ORC_SRT = 1, ORC_TRT = 2, ORC_CUMULANT = 3, ORC_MRT = 4 };
+enum { ORC_NONE = 0, ORC_SRT = 1, ORC_TRT = 2, ORC_CUMULANT = 3, ORC_MRT = 4, ORC_CM = 5 };
 enum { ORC_BC_NOSLIP = 0, ORC_BC_UBB = 1, ORC_BC_PRESSURE = 2 };
 
 typedef struct {
@@ -111,7 +111,7 @@ typedef struct {
   double tau;           /* relaxation time, nu = (tau - 1/2)/3              */
   double magic;         /* TRT magic parameter Lambda                       */
   double omega_bulk;    /* cumulant trace / MRT energy (bulk) rate          */
-  double rates[4];      /* MRT rates of epsilon, pi, q, m moments           */
+  double rates[4];      /* MRT: epsilon, pi, q, m rates; CM: orders 3-6     */
   double force[3];      /* constant body force density F                    */
   int32_t n_classes;    /* boundary classes for labels >= 2                 */
   int32_t cls_type[8];  /* ORC_BC_*                                         */
@@ -218,11 +218,9 @@ static double orc_ipow(double x, int n) {
   return r;
 }
 
-static void orc_collide_cumulant(const orc_stencil* s, const orc_params* P, const double* f,
-                                 double* out) {
-  double rho, u[3];
-  orc_macros(s, f, P->force, &rho, u);
-  double k[3][3][3];
+/* Central moments k_abc about u by direct 27-term sums (step a). */
+static void orc_central_moments(const orc_stencil* s, const double* f, const double u[3],
+                                double k[3][3][3]) {
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b)
       for (int c = 0; c < 3; ++c) {
@@ -232,32 +230,43 @@ static void orc_collide_cumulant(const orc_stencil* s, const orc_params* P, cons
                  orc_ipow(s->c[i][2] - u[2], c);
         k[a][b][c] = acc;
       }
+}
+
+/* Orders 0-2 after collision (steps b, d): density, F/2, and the second
+ * order with off-diagonal and deviatoric parts at omega1 = 1/tau, the trace
+ * towards rho at omega_bulk. */
+static void orc_relax_low_orders(const orc_params* P, double rho, double k[3][3][3],
+                                 double p[3][3][3]) {
   double w1 = 1.0 / P->tau, w2 = P->omega_bulk;
-  double p[3][3][3];
-  memset(p, 0, sizeof(p));
-  /* order 0 and 1 */
+  memset(p, 0, sizeof(double) * 27);
   p[0][0][0] = rho;
   p[1][0][0] = 0.5 * P->force[0];
   p[0][1][0] = 0.5 * P->force[1];
   p[0][0][1] = 0.5 * P->force[2];
-  /* order 2: off-diagonal */
-  double p110 = (1.0 - w1) * k[1][1][0];
-  double p101 = (1.0 - w1) * k[1][0][1];
-  double p011 = (1.0 - w1) * k[0][1][1];
-  /* order 2: deviatoric differences and trace */
+  p[1][1][0] = (1.0 - w1) * k[1][1][0];
+  p[1][0][1] = (1.0 - w1) * k[1][0][1];
+  p[0][1][1] = (1.0 - w1) * k[0][1][1];
   double dxy = (1.0 - w1) * (k[2][0][0] - k[0][2][0]);
   double dxz = (1.0 - w1) * (k[2][0][0] - k[0][0][2]);
   double tr = k[2][0][0] + k[0][2][0] + k[0][0][2];
   tr = tr + w2 * (rho - tr);
-  double p200 = (dxy + dxz + tr) / 3.0;
-  double p020 = (tr - 2.0 * dxy + dxz) / 3.0;
-  double p002 = (tr + dxy - 2.0 * dxz) / 3.0;
-  p[1][1][0] = p110;
-  p[1][0][1] = p101;
-  p[0][1][1] = p011;
-  p[2][0][0] = p200;
-  p[0][2][0] = p020;
-  p[0][0][2] = p002;
+  p[2][0][0] = (dxy + dxz + tr) / 3.0;
+  p[0][2][0] = (tr - 2.0 * dxy + dxz) / 3.0;
+  p[0][0][2] = (tr + dxy - 2.0 * dxz) / 3.0;
+}
+
+static void orc_central_inverse(const orc_stencil* s, double p[3][3][3], const double u[3],
+                                double* out);
+
+static void orc_collide_cumulant(const orc_stencil* s, const orc_params* P, const double* f,
+                                 double* out) {
+  double rho, u[3];
+  orc_macros(s, f, P->force, &rho, u);
+  double k[3][3][3], p[3][3][3];
+  orc_central_moments(s, f, u, k);
+  orc_relax_low_orders(P, rho, k, p);
+  double p110 = p[1][1][0], p101 = p[1][0][1], p011 = p[0][1][1];
+  double p200 = p[2][0][0], p020 = p[0][2][0], p002 = p[0][0][2];
   /* order 3 and 5: zero (already). order 4: */
   p[2][2][0] = (p200 * p020 + 2.0 * p110 * p110) / rho;
   p[2][0][2] = (p200 * p002 + 2.0 * p101 * p101) / rho;
@@ -270,9 +279,13 @@ static void orc_collide_cumulant(const orc_stencil* s, const orc_params* P, cons
                 2.0 * (p110 * p110 * p002 + p101 * p101 * p020 + p011 * p011 * p200) +
                 8.0 * p110 * p101 * p011) /
                (rho * rho);
-  /* e. exact inverse, one axis at a time: central (k0,k1,k2) about v ->
-   * raw (m0,m1,m2) -> values at c = -1, 0, +1. Index 0,1,2 <-> c = 0,+1,-1
-   * is avoided; we store values at position c+1. */
+  orc_central_inverse(s, p, u, out);
+}
+
+/* Step e: exact inverse, one axis at a time: central (k0,k1,k2) about v ->
+ * raw (m0,m1,m2) -> values at c = -1, 0, +1, stored at position c+1. */
+static void orc_central_inverse(const orc_stencil* s, double p[3][3][3], const double u[3],
+                                double* out) {
   double g[3][3][3];
   /* z axis: p[a][b][n] -> g[a][b][cz+1] */
   for (int a = 0; a < 3; ++a)
@@ -313,6 +326,34 @@ static void orc_collide_cumulant(const orc_stencil* s, const orc_params* P, cons
         int i = orc_dir_of(s, x - 1, y - 1, z - 1);
         out[i] = r[x][y][z];
       }
+}
+
+/* Central-moment operator for D3Q27 (the paper names the central-moment
+ * operator among its collision models; the complete per-axis central-moment
+ * basis exists on D3Q27).  Central moments about the local velocity:
+ * orders 0-2 exactly as the cumulant operator (density, F/2, shear at
+ * 1/tau, trace at omega_bulk); every central moment of order n = 3..6
+ * relaxes towards the central moment of the Maxwellian,
+ *   k^eq_abc = rho e(a) e(b) e(c),  e(0) = 1, e(1) = 0, e(2) = 1/3,
+ * with rate rates[n - 3]; back to populations by the exact inverse. */
+static void orc_collide_cm(const orc_stencil* s, const orc_params* P, const double* f,
+                           double* out) {
+  double rho, u[3];
+  orc_macros(s, f, P->force, &rho, u);
+  double k[3][3][3], p[3][3][3];
+  orc_central_moments(s, f, u, k);
+  orc_relax_low_orders(P, rho, k, p);
+  const double e[3] = {1.0, 0.0, 1.0 / 3.0};
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      for (int c = 0; c < 3; ++c) {
+        int n = a + b + c;
+        if (n < 3) continue;
+        double keq = rho * e[a] * e[b] * e[c];
+        double sn = P->rates[n - 3];
+        p[a][b][c] = k[a][b][c] - sn * (k[a][b][c] - keq);
+      }
+  orc_central_inverse(s, p, u, out);
 }
 
 /* Multiple-relaxation-time operator for D3Q19 (the paper lists MRT with
@@ -406,6 +447,7 @@ static void orc_collide(const orc_stencil* s, const orc_params* P, const double*
     case ORC_TRT: orc_collide_trt(s, P, f, out); break;
     case ORC_CUMULANT: orc_collide_cumulant(s, P, f, out); break;
     case ORC_MRT: orc_collide_mrt(s, P, f, out); break;
+    case ORC_CM: orc_collide_cm(s, P, f, out); break;
     default:
       for (int i = 0; i < s->q; ++i) out[i] = f[i];
   }
@@ -415,7 +457,7 @@ static void orc_collide(const orc_stencil* s, const orc_params* P, const double*
 int orc_collide_cells(const orc_params* P, int64_t n, const double* f_in, double* f_out) {
   orc_stencil s;
   if (orc_stencil_init(&s, P->q)) return -1;
-  if (P->kind == ORC_CUMULANT && P->q != 27) return -1;
+  if ((P->kind == ORC_CUMULANT || P->kind == ORC_CM) && P->q != 27) return -1;
   if (P->kind == ORC_MRT && P->q != 19) return -1;
   for (int64_t k = 0; k < n; ++k) orc_collide(&s, P, f_in + k * s.q, f_out + k * s.q);
   return 0;
@@ -471,7 +513,7 @@ int orc_dense_step(const orc_params* P, const uint8_t* labels, int nx, int ny, i
                    uint32_t periodic, const double* A, double* B) {
   orc_stencil s;
   if (orc_stencil_init(&s, P->q)) return -1;
-  if (P->kind == ORC_CUMULANT && P->q != 27) return -1;
+  if ((P->kind == ORC_CUMULANT || P->kind == ORC_CM) && P->q != 27) return -1;
   if (P->kind == ORC_MRT && P->q != 19) return -1;
   const int64_t N = (int64_t)nx * ny * nz;
   const int q = s.q;
@@ -737,7 +779,7 @@ int orc_sparse_step(const orc_params* P, int64_t n_fluid, int64_t S, const int32
                     int64_t n_links, const int32_t* links, int64_t t, double* pdf) {
   orc_stencil s;
   if (orc_stencil_init(&s, P->q)) return -1;
-  if (P->kind == ORC_CUMULANT && P->q != 27) return -1;
+  if ((P->kind == ORC_CUMULANT || P->kind == ORC_CM) && P->q != 27) return -1;
   if (P->kind == ORC_MRT && P->q != 19) return -1;
   const int q = s.q;
   orc_sparse_links(&s, P, n_links, links, pdf);

@@ -82,7 +82,7 @@ def _random_states(q, n, seed, amp=1e-2):
 
 
 KINDS = [(19, oracle.SRT), (19, oracle.TRT), (27, oracle.SRT), (27, oracle.TRT),
-         (27, oracle.CUMULANT), (19, oracle.MRT)]
+         (27, oracle.CUMULANT), (19, oracle.MRT), (27, oracle.CM)]
 
 
 @pytest.mark.parametrize("q,kind", KINDS)
@@ -107,7 +107,7 @@ def test_equilibrium_fixed_point(q, kind):
     for _ in range(10):
         rho = 1.0 + 0.1 * rng.standard_normal()
         u = 0.08 * rng.standard_normal(3)
-        f = (_product_eq if kind == oracle.CUMULANT else _feq)(q, rho, u)
+        f = (_product_eq if kind in (oracle.CUMULANT, oracle.CM) else _feq)(q, rho, u)
         fs = oracle.collide(p, f[None])[0]
         assert np.max(np.abs(fs - f)) < 5e-16
 
@@ -330,3 +330,79 @@ def test_mrt_relaxes_each_moment_group_at_its_rate():
                 assert abs(ms[k] - m[k]) < 1e-15
             else:
                 assert abs((ms[k] - meq[k]) - (1 - rate[k]) * (m[k] - meq[k])) < 1e-14
+
+
+# ----------------------------------------------------- central moments
+def _central(f, c, u):
+    """Central moments k[a, b, g] = sum_i f_i (c - u)_x^a (c - u)_y^b (c - u)_z^g."""
+    d = c.astype(float) - u[None, :]
+    K = np.zeros((3, 3, 3))
+    for a, b, g in itertools.product(range(3), repeat=3):
+        K[a, b, g] = np.sum(f * d[:, 0] ** a * d[:, 1] ** b * d[:, 2] ** g)
+    return K
+
+
+def test_cm_relaxes_each_order_to_the_maxwellian():
+    """Unforced: central moments of order n = 3..6 approach the Maxwellian's
+    (rho times 1, 0, 1/3 per axis for exponents 0, 1, 2) by the factor
+    (1 - rate_n); orders 0-2 follow the cumulant operator's rules, which the
+    cumulant test pins (same second order)."""
+    q = 27
+    c, _, _ = oracle.stencil(q)
+    tau, wb, rates = 0.7, 1.3, (1.2, 0.8, 1.5, 1.9)
+    e = (1.0, 0.0, 1.0 / 3.0)
+    f = _random_states(q, 20, seed=19, amp=5e-2)
+    fs = oracle.collide(oracle.params(q=q, kind=oracle.CM, tau=tau, omega_bulk=wb,
+                                      rates=rates), f)
+    cu = oracle.collide(oracle.params(q=q, kind=oracle.CUMULANT, tau=tau, omega_bulk=wb), f)
+    for k in range(f.shape[0]):
+        rho = f[k].sum()
+        u = (c.T @ f[k]) / rho
+        K, Ks, Kc = _central(f[k], c, u), _central(fs[k], c, u), _central(cu[k], c, u)
+        for a, b, g in itertools.product(range(3), repeat=3):
+            n = a + b + g
+            if n <= 2:
+                assert abs(Ks[a, b, g] - Kc[a, b, g]) < 1e-15
+            else:
+                keq = rho * e[a] * e[b] * e[g]
+                assert abs((Ks[a, b, g] - keq) - (1 - rates[n - 3]) * (K[a, b, g] - keq)) < 1e-15
+
+
+def test_cm_unit_rates_give_product_equilibrium():
+    """All rates one and F = 0: every central moment takes the Maxwellian
+    value, which the product-form equilibrium has exactly -- the same state
+    the cumulant operator reaches at unit rates."""
+    q = 27
+    c, _, _ = oracle.stencil(q)
+    f = _random_states(q, 25, seed=23, amp=5e-2)
+    fs = oracle.collide(oracle.params(q=q, kind=oracle.CM, tau=1.0, omega_bulk=1.0,
+                                      rates=(1, 1, 1, 1)), f)
+    for k in range(f.shape[0]):
+        rho = f[k].sum()
+        u = (c.T @ f[k]) / rho
+        assert np.max(np.abs(fs[k] - _product_eq(q, rho, u))) < 1e-15
+
+
+def test_cm_at_rest_with_equal_rates_is_srt():
+    """At u = 0 and F = 0 the central moments are raw moments and the
+    Maxwellian's equal the moments of f^eq = w rho (the D3Q27 weights carry
+    them up to sixth order), so every rate = omega reduces the operator to
+    SRT."""
+    q = 27
+    c, w, _ = oracle.stencil(q)
+    rng = np.random.default_rng(29)
+    tau = 0.74
+    om = 1 / tau
+    for _ in range(10):
+        f = w * (1 + 0.05 * rng.standard_normal(q))
+        f -= w * ((c.T @ f) @ c.T) * 3       # remove the momentum: u = 0 exactly
+        assert np.max(np.abs(c.T @ f)) < 1e-16
+        a = oracle.collide(oracle.params(q=q, kind=oracle.CM, tau=tau, omega_bulk=om,
+                                         rates=(om,) * 4), f[None])[0]
+        b = oracle.collide(oracle.params(q=q, kind=oracle.SRT, tau=tau), f[None])[0]
+        assert np.max(np.abs(a - b)) < 1e-15
+
+
+def test_cm_rejects_d3q19():
+    with pytest.raises(RuntimeError):
+        oracle.collide(oracle.params(q=19, kind=oracle.CM), _random_states(19, 1, 0))

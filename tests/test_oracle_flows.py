@@ -83,7 +83,7 @@ def _shear_wave_rate(kind, tau, L, U0=0.0, q=27, steps=(200, 600)):
     u = np.zeros((3, 1, L, 1))
     U = 1e-4
     u[0, 0, :, 0] = U0 + U * np.sin(2 * np.pi * y / L)
-    eq = _product_eq_field if kind == oracle.CUMULANT else _feq_field
+    eq = _product_eq_field if kind in (oracle.CUMULANT, oracle.CM) else _feq_field
     A = eq(q, rho, u)
     p = oracle.params(q=q, kind=kind, tau=tau, magic=3.0 / 16.0)
     amps = []
@@ -99,7 +99,7 @@ def _shear_wave_rate(kind, tau, L, U0=0.0, q=27, steps=(200, 600)):
 
 
 @pytest.mark.parametrize("kind,q", [(oracle.SRT, 19), (oracle.TRT, 19), (oracle.CUMULANT, 27),
-                                    (oracle.MRT, 19)])
+                                    (oracle.MRT, 19), (oracle.CM, 27)])
 def test_shear_wave_viscosity(kind, q):
     """A shear wave decays as exp(-nu k^2 t); the lattice error is O(k^2), so
     the relative rate error must shrink about 4x when L doubles."""
@@ -109,10 +109,12 @@ def test_shear_wave_viscosity(kind, q):
     assert e64 < 0.35 * e32 or e64 < 1e-6
 
 
-def test_cumulant_shear_wave_galilean():
-    """Cumulant: the same decay rate on top of a uniform background flow."""
-    r0 = _shear_wave_rate(oracle.CUMULANT, 0.8, 32, steps=(100, 300))
-    r1 = _shear_wave_rate(oracle.CUMULANT, 0.8, 32, U0=0.05, steps=(100, 300))
+@pytest.mark.parametrize("kind", [oracle.CUMULANT, oracle.CM])
+def test_shear_wave_galilean(kind):
+    """Cumulant and central moments: the same decay rate on top of a
+    uniform background flow."""
+    r0 = _shear_wave_rate(kind, 0.8, 32, steps=(100, 300))
+    r1 = _shear_wave_rate(kind, 0.8, 32, U0=0.05, steps=(100, 300))
     assert abs(r1 - r0) < 2e-2
 
 
