@@ -254,8 +254,9 @@ def main():
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--pipelined", type=int, default=0, choices=[0, 1],
                     help="odd kernel as persistent workgroups prefetching the next tile")
-    ap.add_argument("--coll", default="trt", choices=["trt", "srt", "mrt"],
-                    help="packing workload: collision operator (D3Q19)")
+    ap.add_argument("--coll", default="trt", choices=["trt", "srt", "mrt", "cumulant", "cm"],
+                    help="packing workload: collision operator (D3Q19; cumulant and "
+                         "central moments on D3Q27)")
     ap.add_argument("--even-cells", type=int, default=0, choices=[0, 1, 2],
                     help="cells per thread of the even-step kernel (0: the library's "
                          "default, two for 16-bit storage)")
@@ -324,6 +325,8 @@ def main():
     order = {"morton": lbm.ORDER_MORTON, "lex": lbm.ORDER_LEX,
              "blocked": lbm.ORDER_BLOCKED}[args.order]
     q, magic, force = 19, 3.0 / 16.0, (1e-6, 0.0, 0.0)
+    if args.coll in ("cumulant", "cm"):
+        q = 27
     torch.cuda.set_device(0)
     vessel = args.workload == "vessel"
     bs = None
@@ -368,7 +371,8 @@ def main():
     if vessel:
         coll = lbm.collision(lbm.COLL_CUMULANT, tau=0.8, omega_bulk=1.0, force=force)
     else:
-        kind = {"trt": lbm.COLL_TRT, "srt": lbm.COLL_SRT, "mrt": lbm.COLL_MRT}[args.coll]
+        kind = {"trt": lbm.COLL_TRT, "srt": lbm.COLL_SRT, "mrt": lbm.COLL_MRT,
+                "cumulant": lbm.COLL_CUMULANT, "cm": lbm.COLL_CM}[args.coll]
         coll = lbm.collision(kind, tau=args.tau, magic=magic, force=force, omega_bulk=1.19)
     sol.init()
     sol.step(args.warmup, coll, bs)
@@ -465,7 +469,7 @@ def main():
         log(f"cpu oracle {cpu['value']:.1f} MFLUPS on {cpu['cores']} threads")
 
     achieved = nf * b_odd / t_odd / 1e9
-    workload = (f"sparse D3Q19 {args.coll.upper()} AA, {args.L}^3 periodic overlapping-sphere packing "
+    workload = (f"sparse D3Q{q} {args.coll.upper()} AA, {args.L}^3 periodic overlapping-sphere packing "
                 f"phi={info['phi']:.3f} (r 4-12, seed {info['seed']})")
     if vessel:
         workload = (f"sparse D3Q27 cumulant AA (tau 0.8), {args.L}^3 vessel tree "

@@ -62,7 +62,7 @@ typedef int32_t lbm_status;
 
 enum { LBM_D3Q19 = 19, LBM_D3Q27 = 27 };
 enum { LBM_COLL_NONE = 0, LBM_COLL_SRT = 1, LBM_COLL_TRT = 2, LBM_COLL_CUMULANT = 3,
-       LBM_COLL_MRT = 4 };
+       LBM_COLL_MRT = 4, LBM_COLL_CM = 5 };
 /* Storage of the PDF-list.  *DEV formats store the deviation f_i - w_i
  * from the rest weights ("zero-centred" storage option, Section "Code
  * Generation for Sparse Kernels"), 16-bit ones scaled by 2^dev_exp.  All
@@ -167,6 +167,12 @@ typedef struct {
  *            energy flux q and third-order m with rates[0..3] (each in
  *            (0, 2)); the Guo source enters every moment with (1 - s/2).
  *            Even rates = 1/tau and odd rates = omega- give TRT exactly.
+ *  CM:       central moments, D3Q27 only (the stencil with the complete
+ *            per-axis central-moment basis); orders 0-2 as CUMULANT, each
+ *            central moment of order n = 3..6 relaxes towards the
+ *            Maxwellian's (rho times 1, 0, 1/3 per axis for exponent 0, 1,
+ *            2) with rates[n - 3], each in (0, 2); all rates one give the
+ *            product-form equilibrium, as the cumulant operator does.
  *  force:    constant body force density (Guo scheme, half-force velocity).
  */
 typedef struct {
@@ -176,7 +182,7 @@ typedef struct {
   double magic;          /* TRT Lambda, e.g. 3/16                               */
   double omega_bulk;     /* cumulant trace rate, MRT energy rate, e.g. 1       */
   double force[3];
-  double rates[4];       /* MRT only: rates of the epsilon, pi, q, m moments    */
+  double rates[4];       /* MRT: epsilon, pi, q, m rates; CM: orders 3, 4, 5, 6 */
 } lbm_collision;
 
 /* Boundary classes for labels 2..9.  UBB: moving wall u (bounce-back plus

@@ -101,7 +101,7 @@ lbm_status check_state(const lbm_state* s) {
 
 lbm_status check_coll(const lbm_collision* c, int q) {
   if (!c) return fail(LBM_EINVAL, "collision is NULL");
-  if (c->kind < LBM_COLL_NONE || c->kind > LBM_COLL_MRT)
+  if (c->kind < LBM_COLL_NONE || c->kind > LBM_COLL_CM)
     return fail(LBM_EINVAL, "unknown collision kind %d", c->kind);
   if (c->kind != LBM_COLL_NONE && !(c->tau > 0.5))
     return fail(LBM_EINVAL, "tau must be > 1/2 (got %g)", c->tau);
@@ -109,15 +109,17 @@ lbm_status check_coll(const lbm_collision* c, int q) {
     return fail(LBM_EINVAL, "TRT magic parameter must be > 0 (got %g)", c->magic);
   if (c->kind == LBM_COLL_CUMULANT && q != 27)
     return fail(LBM_EINVAL, "the cumulant operator needs D3Q27");
-  if ((c->kind == LBM_COLL_CUMULANT || c->kind == LBM_COLL_MRT) &&
+  if ((c->kind == LBM_COLL_CUMULANT || c->kind == LBM_COLL_MRT || c->kind == LBM_COLL_CM) &&
       !(c->omega_bulk > 0.0 && c->omega_bulk < 2.0))
     return fail(LBM_EINVAL, "omega_bulk must be in (0, 2) (got %g)", c->omega_bulk);
   if (c->kind == LBM_COLL_MRT && q != 19)
     return fail(LBM_EINVAL, "the MRT operator needs D3Q19");
-  if (c->kind == LBM_COLL_MRT)
+  if (c->kind == LBM_COLL_CM && q != 27)
+    return fail(LBM_EINVAL, "the central-moment operator needs D3Q27");
+  if (c->kind == LBM_COLL_MRT || c->kind == LBM_COLL_CM)
     for (int a = 0; a < 4; ++a)
       if (!(c->rates[a] > 0.0 && c->rates[a] < 2.0))
-        return fail(LBM_EINVAL, "MRT rates must be in (0, 2) (rates[%d] = %g)", a, c->rates[a]);
+        return fail(LBM_EINVAL, "rates must be in (0, 2) (rates[%d] = %g)", a, c->rates[a]);
   for (int a = 0; a < 3; ++a)
     if (!isfinite(c->force[a])) return fail(LBM_EINVAL, "force must be finite");
   return LBM_OK;
@@ -125,13 +127,14 @@ lbm_status check_coll(const lbm_collision* c, int q) {
 
 void coll_rates(const lbm_collision* c, double& om1, double& om2, double* rates) {
   om1 = om2 = 0.0;
-  for (int a = 0; a < 4; ++a) rates[a] = c->kind == LBM_COLL_MRT ? c->rates[a] : 0.0;
+  const bool has_rates = c->kind == LBM_COLL_MRT || c->kind == LBM_COLL_CM;
+  for (int a = 0; a < 4; ++a) rates[a] = has_rates ? c->rates[a] : 0.0;
   if (c->kind == LBM_COLL_SRT) {
     om1 = om2 = 1.0 / c->tau;
   } else if (c->kind == LBM_COLL_TRT) {
     om1 = 1.0 / c->tau;
     om2 = 1.0 / (0.5 + c->magic / (c->tau - 0.5));
-  } else if (c->kind == LBM_COLL_CUMULANT || c->kind == LBM_COLL_MRT) {
+  } else if (c->kind == LBM_COLL_CUMULANT || c->kind == LBM_COLL_MRT || c->kind == LBM_COLL_CM) {
     om1 = 1.0 / c->tau;
     om2 = c->omega_bulk;
   }

@@ -15,13 +15,15 @@
 
 namespace lbm {
 
-enum CollKind { COLL_NONE = 0, COLL_SRT = 1, COLL_TRT = 2, COLL_CUMULANT = 3, COLL_MRT = 4 };
+enum CollKind {
+  COLL_NONE = 0, COLL_SRT = 1, COLL_TRT = 2, COLL_CUMULANT = 3, COLL_MRT = 4, COLL_CM = 5
+};
 
 template <class R>
 struct CollParams {
-  R om1, om2;  // SRT: omega; TRT: omega+, omega-; cumulant, MRT: shear, bulk
+  R om1, om2;  // SRT: omega; TRT: omega+, omega-; cumulant, MRT, CM: shear, bulk
   R Fx, Fy, Fz;
-  R r[4];      // MRT: epsilon, pi, q, m rates
+  R r[4];      // MRT: epsilon, pi, q, m rates; CM: orders 3-6
 };
 
 template <int Q, class R>

@@ -44,15 +44,14 @@ __device__ __forceinline__ void chimera_bwd(R& a, R& b, R& c, R v) {
   c = R(0.5) * (m2 + m1);
 }
 
+// Deviations d (indexed by direction) -> central moments K^d[a][b][c] of
+// the deviations about u: z, y, x axis passes.
 template <class R>
-__device__ __forceinline__ void collide_cumulant(R (&d)[27], const CollParams<R>& p) {
+__device__ __forceinline__ void central_forward(const R (&d)[27], R ux, R uy, R uz,
+                                                R (&m)[3][3][3]) {
   using L = Lattice<27>;
-  const Macro<27, R> mac = macros<27, R>(d, p);
-  const R ux = mac.ux, uy = mac.uy, uz = mac.uz;
-  R m[3][3][3];
 #pragma unroll
   for (int i = 0; i < 27; ++i) m[L::cx[i] + 1][L::cy[i] + 1][L::cz[i] + 1] = d[i];
-  // forward: z, y, x
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -65,37 +64,90 @@ __device__ __forceinline__ void collide_cumulant(R (&d)[27], const CollParams<R>
   for (int b = 0; b < 3; ++b)
 #pragma unroll
     for (int c = 0; c < 3; ++c) chimera_fwd(m[0][b][c], m[1][b][c], m[2][b][c], ux);
+}
 
+// Post-collision deviation moments D*[a][b][c] -> deviations d*: x, y, z
+// axis passes of the exact inverse.
+template <class R>
+__device__ __forceinline__ void central_backward(R (&D)[3][3][3], R ux, R uy, R uz,
+                                                 R (&d)[27]) {
+  using L = Lattice<27>;
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) chimera_bwd(D[0][b][c], D[1][b][c], D[2][b][c], ux);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) chimera_bwd(D[a][0][c], D[a][1][c], D[a][2][c], uy);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) chimera_bwd(D[a][b][0], D[a][b][1], D[a][b][2], uz);
+#pragma unroll
+  for (int i = 0; i < 27; ++i) d[i] = D[L::cx[i] + 1][L::cy[i] + 1][L::cz[i] + 1];
+}
+
+// Orders 0-2 after collision, written as deviations D* = K* - K^w (shared
+// by the cumulant and central-moment operators): density, F/2 for the
+// first order, off-diagonal and deviatoric second order at om1, the trace
+// towards rho at om2.  Also returns the post-collision full second-order
+// moments' small parts used by the cumulant's higher orders.
+template <class R>
+struct LowOrders {
+  R a2, b2, c2, e0, f0, g0;  // D* of 200, 020, 002, 110, 101, 011
+};
+
+template <class R>
+__device__ __forceinline__ LowOrders<R> relax_low_orders(const R (&m)[3][3][3],
+                                                         const Macro<27, R>& mac,
+                                                         const CollParams<R>& p,
+                                                         R (&D)[3][3][3]) {
+  const R ux = mac.ux, uy = mac.uy, uz = mac.uz;
   const R w1 = p.om1, w2 = p.om2;
-  const R drho = mac.drho, rho = mac.rho, inv_rho = R(1) / rho;
+  const R drho = mac.drho;
   const R ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz;
-  const R A = R(1) / R(3) + ux2, B = R(1) / R(3) + uy2, C = R(1) / R(3) + uz2;
-
-  // second order
-  const R e0 = (R(1) - w1) * m[1][1][0] - w1 * ux * uy;
-  const R f0 = (R(1) - w1) * m[1][0][1] - w1 * ux * uz;
-  const R g0 = (R(1) - w1) * m[0][1][1] - w1 * uy * uz;
+  LowOrders<R> o;
+  o.e0 = (R(1) - w1) * m[1][1][0] - w1 * ux * uy;
+  o.f0 = (R(1) - w1) * m[1][0][1] - w1 * ux * uz;
+  o.g0 = (R(1) - w1) * m[0][1][1] - w1 * uy * uz;
   const R dxy = (R(1) - w1) * ((ux2 - uy2) + (m[2][0][0] - m[0][2][0]));
   const R dxz = (R(1) - w1) * ((ux2 - uz2) + (m[2][0][0] - m[0][0][2]));
   const R tm1 = (R(1) - w2) * ((ux2 + uy2 + uz2) + (m[2][0][0] + m[0][2][0] + m[0][0][2])) +
                 w2 * drho;
-  const R a2 = (dxy + dxz + tm1) * (R(1) / R(3)) - ux2;
-  const R b2 = (tm1 - R(2) * dxy + dxz) * (R(1) / R(3)) - uy2;
-  const R c2 = (tm1 + dxy - R(2) * dxz) * (R(1) / R(3)) - uz2;
-  const R e = ux * uy + e0, f = ux * uz + f0, g = uy * uz + g0;
-  const R Ap = A + a2, Bp = B + b2, Cp = C + c2;
-
-  R D[3][3][3];
+  o.a2 = (dxy + dxz + tm1) * (R(1) / R(3)) - ux2;
+  o.b2 = (tm1 - R(2) * dxy + dxz) * (R(1) / R(3)) - uy2;
+  o.c2 = (tm1 + dxy - R(2) * dxz) * (R(1) / R(3)) - uz2;
   D[0][0][0] = drho;
   D[1][0][0] = R(0.5) * p.Fx + ux;
   D[0][1][0] = R(0.5) * p.Fy + uy;
   D[0][0][1] = R(0.5) * p.Fz + uz;
-  D[1][1][0] = e0;
-  D[1][0][1] = f0;
-  D[0][1][1] = g0;
-  D[2][0][0] = a2;
-  D[0][2][0] = b2;
-  D[0][0][2] = c2;
+  D[1][1][0] = o.e0;
+  D[1][0][1] = o.f0;
+  D[0][1][1] = o.g0;
+  D[2][0][0] = o.a2;
+  D[0][2][0] = o.b2;
+  D[0][0][2] = o.c2;
+  return o;
+}
+
+template <class R>
+__device__ __forceinline__ void collide_cumulant(R (&d)[27], const CollParams<R>& p) {
+  const Macro<27, R> mac = macros<27, R>(d, p);
+  const R ux = mac.ux, uy = mac.uy, uz = mac.uz;
+  R m[3][3][3];
+  central_forward(d, ux, uy, uz, m);
+
+  const R drho = mac.drho, rho = mac.rho, inv_rho = R(1) / rho;
+  const R ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz;
+  const R A = R(1) / R(3) + ux2, B = R(1) / R(3) + uy2, C = R(1) / R(3) + uz2;
+
+  R D[3][3][3];
+  const LowOrders<R> lo = relax_low_orders(m, mac, p, D);
+  const R e0 = lo.e0, f0 = lo.f0, g0 = lo.g0, a2 = lo.a2, b2 = lo.b2, c2 = lo.c2;
+  // second order (full moments' small parts)
+  const R e = ux * uy + e0, f = ux * uz + f0, g = uy * uz + g0;
+  const R Ap = A + a2, Bp = B + b2, Cp = C + c2;
   // third order: K* = 0  ->  D* = -K^w
   D[1][1][1] = ux * uy * uz;
   D[2][1][0] = A * uy;
@@ -124,21 +176,59 @@ __device__ __forceinline__ void collide_cumulant(R (&d)[27], const CollParams<R>
     D[2][2][2] = (lin + quad + cub - drho * (R(2) + drho) * A * B * C + iss) * (inv_rho * inv_rho);
   }
 
-  // backward: x, y, z
-#pragma unroll
-  for (int b = 0; b < 3; ++b)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) chimera_bwd(D[0][b][c], D[1][b][c], D[2][b][c], ux);
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) chimera_bwd(D[a][0][c], D[a][1][c], D[a][2][c], uy);
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) chimera_bwd(D[a][b][0], D[a][b][1], D[a][b][2], uz);
-#pragma unroll
-  for (int i = 0; i < 27; ++i) d[i] = D[L::cx[i] + 1][L::cy[i] + 1][L::cz[i] + 1];
+  central_backward(D, ux, uy, uz, d);
+}
+
+// Central-moment operator for D3Q27 (the paper names the central-moment
+// model among its operators; D3Q27 holds the complete per-axis basis).
+// Orders 0-2 as the cumulant operator; every central moment of order
+// n = 3..6 relaxes towards the Maxwellian's, K^eq_abc = rho e(a) e(b) e(c)
+// with e = (1, 0, 1/3), at rate p.r[n - 3]:
+//   D* = K* - K^w = (1 - s) K^d + s (K^eq - K^w),
+// with K^eq - K^w in closed form of the small quantities (drho, u):
+//   any exponent 1:  K^eq = 0, K^w = product of k(a, u_a), k(1, u) = -u;
+//   220-type:        rho/9  - A B   = drho/9 - (ux^2 + uy^2)/3 - ux^2 uy^2;
+//   222:             rho/27 - A B C = drho/27 - |u|^2/9
+//                                     - (ux^2 uy^2 + ux^2 uz^2 + uy^2 uz^2)/3
+//                                     - ux^2 uy^2 uz^2.
+template <class R>
+__device__ __forceinline__ void collide_cm(R (&d)[27], const CollParams<R>& p) {
+  const Macro<27, R> mac = macros<27, R>(d, p);
+  const R ux = mac.ux, uy = mac.uy, uz = mac.uz;
+  R m[3][3][3];
+  central_forward(d, ux, uy, uz, m);
+  R D[3][3][3];
+  relax_low_orders(m, mac, p, D);
+  const R drho = mac.drho;
+  const R ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz;
+  const R A = R(1) / R(3) + ux2, B = R(1) / R(3) + uy2, C = R(1) / R(3) + uz2;
+  const R s3 = p.r[0], s4 = p.r[1], s5 = p.r[2], s6 = p.r[3];
+  const R t3 = R(1) - s3, t4 = R(1) - s4, t5 = R(1) - s5, t6 = R(1) - s6;
+  // order 3: K^eq = 0, D* = (1 - s3) K^d - s3 K^w
+  D[1][1][1] = t3 * m[1][1][1] + s3 * (ux * uy * uz);
+  D[2][1][0] = t3 * m[2][1][0] + s3 * (A * uy);
+  D[2][0][1] = t3 * m[2][0][1] + s3 * (A * uz);
+  D[1][2][0] = t3 * m[1][2][0] + s3 * (B * ux);
+  D[0][2][1] = t3 * m[0][2][1] + s3 * (B * uz);
+  D[1][0][2] = t3 * m[1][0][2] + s3 * (C * ux);
+  D[0][1][2] = t3 * m[0][1][2] + s3 * (C * uy);
+  // order 4
+  const R r9 = R(1) / R(9), r3 = R(1) / R(3);
+  D[2][2][0] = t4 * m[2][2][0] + s4 * (drho * r9 - (ux2 + uy2) * r3 - ux2 * uy2);
+  D[2][0][2] = t4 * m[2][0][2] + s4 * (drho * r9 - (ux2 + uz2) * r3 - ux2 * uz2);
+  D[0][2][2] = t4 * m[0][2][2] + s4 * (drho * r9 - (uy2 + uz2) * r3 - uy2 * uz2);
+  D[2][1][1] = t4 * m[2][1][1] - s4 * (A * uy * uz);
+  D[1][2][1] = t4 * m[1][2][1] - s4 * (B * ux * uz);
+  D[1][1][2] = t4 * m[1][1][2] - s4 * (C * ux * uy);
+  // order 5: K^w_221 = -A B uz
+  D[2][2][1] = t5 * m[2][2][1] + s5 * (A * B * uz);
+  D[2][1][2] = t5 * m[2][1][2] + s5 * (A * C * uy);
+  D[1][2][2] = t5 * m[1][2][2] + s5 * (B * C * ux);
+  // order 6
+  D[2][2][2] = t6 * m[2][2][2] +
+               s6 * (drho * (R(1) / R(27)) - (ux2 + uy2 + uz2) * r9 -
+                     (ux2 * uy2 + ux2 * uz2 + uy2 * uz2) * r3 - ux2 * uy2 * uz2);
+  central_backward(D, ux, uy, uz, d);
 }
 
 }  // namespace lbm

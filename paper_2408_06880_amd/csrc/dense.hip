@@ -140,6 +140,7 @@ hipError_t launch_dense_step(int q, int coll, int storage, bool odd, const Dense
     if (coll == COLL_SRT) return launch_dense_qc<27, COLL_SRT>(storage, odd, a, block, st);
     if (coll == COLL_TRT) return launch_dense_qc<27, COLL_TRT>(storage, odd, a, block, st);
     if (coll == COLL_CUMULANT) return launch_dense_qc<27, COLL_CUMULANT>(storage, odd, a, block, st);
+    if (coll == COLL_CM) return launch_dense_qc<27, COLL_CM>(storage, odd, a, block, st);
     if (coll == COLL_NONE) return launch_dense_qc<27, COLL_NONE>(storage, odd, a, block, st);
   }
   return hipErrorInvalidValue;

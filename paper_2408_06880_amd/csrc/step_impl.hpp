@@ -36,6 +36,9 @@ __device__ __forceinline__ void collide(R (&d)[Q], const CollParams<R>& p) {
   } else if constexpr (COLL == COLL_CUMULANT) {
     static_assert(Q == 27, "cumulant needs D3Q27");
     collide_cumulant<R>(d, p);
+  } else if constexpr (COLL == COLL_CM) {
+    static_assert(Q == 27, "central moments need D3Q27");
+    collide_cm<R>(d, p);
   } else if constexpr (COLL == COLL_MRT) {
     static_assert(Q == 19, "MRT is defined for D3Q19");
     collide_mrt<R>(d, p);

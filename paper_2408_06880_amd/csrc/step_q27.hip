@@ -11,6 +11,7 @@ hipError_t launch_aa_q27(int coll, int storage, int mode, int idx, const StepArg
     case COLL_SRT: return launch_aa_c<27, COLL_SRT>(storage, mode, idx, a, block, st);
     case COLL_TRT: return launch_aa_c<27, COLL_TRT>(storage, mode, idx, a, block, st);
     case COLL_CUMULANT: return launch_aa_c<27, COLL_CUMULANT>(storage, mode, idx, a, block, st);
+    case COLL_CM: return launch_aa_c<27, COLL_CM>(storage, mode, idx, a, block, st);
   }
   return hipErrorInvalidValue;
 }

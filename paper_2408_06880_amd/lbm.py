@@ -25,9 +25,11 @@ LIB_PATH = os.environ.get("LBM_LIBRARY") or os.path.join(_PKG, "liblbm.so")
 LBM_OK, LBM_EINVAL, LBM_ERANGE, LBM_ENOMEM = 0, -1, -2, -3
 LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = -4, -5, -6
 D3Q19, D3Q27 = 19, 27
-COLL_NONE, COLL_SRT, COLL_TRT, COLL_CUMULANT, COLL_MRT = 0, 1, 2, 3, 4
+COLL_NONE, COLL_SRT, COLL_TRT, COLL_CUMULANT, COLL_MRT, COLL_CM = 0, 1, 2, 3, 4, 5
 # MRT rates of the epsilon, pi, q and m moments suggested by d'Humieres et al. (2002)
 MRT_RATES = (1.4, 1.4, 1.2, 1.98)
+# central-moment rates of orders 3-6: all one (higher moments at equilibrium)
+CM_RATES = (1.0, 1.0, 1.0, 1.0)
 STORE_F64, STORE_F32, STORE_F16DEV, STORE_BF16DEV, STORE_F32DEV = 0, 1, 2, 3, 4
 ORDER_MORTON, ORDER_LEX, ORDER_BLOCKED = 0, 1, 2
 BC_NOSLIP, BC_UBB, BC_PRESSURE = 0, 1, 2
@@ -325,8 +327,11 @@ def lbm_copy(dst, src, nbytes, stream=None):
 
 # ------------------------------------------------------- conveniences
 def collision(kind=COLL_TRT, tau=0.8, magic=3.0 / 16.0, omega_bulk=1.0, force=(0.0, 0.0, 0.0),
-              rates=MRT_RATES):
-    """rates: MRT only (epsilon, pi, q, m groups)."""
+              rates=None):
+    """rates: MRT epsilon, pi, q, m groups, or central-moment orders 3-6
+    (default per kind)."""
+    if rates is None:
+        rates = CM_RATES if kind == COLL_CM else MRT_RATES
     c = lbm_collision()
     c.kind, c.tau, c.magic, c.omega_bulk = kind, tau, magic, omega_bulk
     for a in range(3):

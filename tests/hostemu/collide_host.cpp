@@ -21,6 +21,7 @@ static void run(const double* P, long n, const double* fin, double* fout) {
     if constexpr (C == COLL_TRT) collide_trt<Q, R>(d, p);
     if constexpr (C == COLL_CUMULANT && Q == 27) collide_cumulant<R>(d, p);
     if constexpr (C == COLL_MRT && Q == 19) collide_mrt<R>(d, p);
+    if constexpr (C == COLL_CM && Q == 27) collide_cm<R>(d, p);
     for (int i = 0; i < Q; ++i) fout[k * Q + i] = Lattice<Q>::w(i) + (double)d[i];
   }
 }
@@ -41,5 +42,6 @@ extern "C" int host_collide(int q, int kind, int f64, const double* P, long n, c
   DISPATCH(27, COLL_TRT)
   DISPATCH(27, COLL_CUMULANT)
   DISPATCH(19, COLL_MRT)
+  DISPATCH(27, COLL_CM)
   return -1;
 }

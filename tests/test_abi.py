@@ -86,6 +86,11 @@ def test_invalid_arguments_rejected_on_host():
            lbm.collision(lbm.COLL_MRT, tau=0.8, rates=(1.4, 1.4, 2.0, 1.0)), None, 0)
     expect(lbm.LBM_EINVAL, lbm.lbm_step, _fake_state(), 1,
            lbm.collision(lbm.COLL_MRT, tau=0.8, omega_bulk=0.0), None, 0)
+    # central moments: D3Q27 only
+    expect(lbm.LBM_EINVAL, lbm.lbm_step, _fake_state(q=19), 1,
+           lbm.collision(lbm.COLL_CM, tau=0.8), None, 0)
+    expect(lbm.LBM_EINVAL, lbm.lbm_step, _fake_state(q=27), 1,
+           lbm.collision(lbm.COLL_CM, tau=0.8, rates=(1, 1, 0, 1)), None, 0)
     st = _fake_state(storage=lbm.STORE_F16DEV)
     st.dev_exp = 30
     expect(lbm.LBM_EINVAL, lbm.lbm_step, st, 1, lbm.collision(), None, 0)

@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 from paper_2408_06880_amd import lbm  # noqa: E402
 
 KIND = {lbm.COLL_NONE: oracle.NONE, lbm.COLL_SRT: oracle.SRT, lbm.COLL_TRT: oracle.TRT,
-        lbm.COLL_CUMULANT: oracle.CUMULANT, lbm.COLL_MRT: oracle.MRT}
+        lbm.COLL_CUMULANT: oracle.CUMULANT, lbm.COLL_MRT: oracle.MRT, lbm.COLL_CM: oracle.CM}
 BC = {lbm.BC_NOSLIP: oracle.BC_NOSLIP, lbm.BC_UBB: oracle.BC_UBB,
       lbm.BC_PRESSURE: oracle.BC_PRESSURE}
 
@@ -44,6 +44,8 @@ def _check_index(dom):
 
 def _params(q, kind, tau, force, classes, magic=3.0 / 16.0, omega_bulk=1.0,
             rates=(1.3, 1.5, 1.2, 1.7)):
+    """Collision (library), boundary spec and oracle parameters of one case;
+    `rates` are the MRT group rates or the central-moment order rates."""
     coll = lbm.collision(kind, tau=tau, magic=magic, omega_bulk=omega_bulk, force=force,
                          rates=rates)
     bs = lbm.bspec(classes)
@@ -168,7 +170,8 @@ AA_CASES = [
     (19, lbm.COLL_TRT, lbm.STORE_F32DEV), (27, lbm.COLL_CUMULANT, lbm.STORE_F32),
     (27, lbm.COLL_CUMULANT, lbm.STORE_F32DEV), (27, lbm.COLL_TRT, lbm.STORE_F32),
     (19, lbm.COLL_MRT, lbm.STORE_F64), (19, lbm.COLL_MRT, lbm.STORE_F32),
-    (19, lbm.COLL_MRT, lbm.STORE_F32DEV),
+    (19, lbm.COLL_MRT, lbm.STORE_F32DEV), (27, lbm.COLL_CM, lbm.STORE_F64),
+    (27, lbm.COLL_CM, lbm.STORE_F32),
 ]
 
 
@@ -207,7 +210,8 @@ def test_aa_steps_match_oracle(q, kind, storage):
 
 
 @pytest.mark.parametrize("q,kind", [(19, lbm.COLL_TRT), (19, lbm.COLL_SRT),
-                                    (27, lbm.COLL_CUMULANT), (19, lbm.COLL_MRT)])
+                                    (27, lbm.COLL_CUMULANT), (19, lbm.COLL_MRT),
+                                    (27, lbm.COLL_CM)])
 @pytest.mark.parametrize("storage,dev_exp", [(lbm.STORE_F16DEV, 14), (lbm.STORE_F16DEV, 10),
                                              (lbm.STORE_BF16DEV, 0)])
 def test_16bit_one_step_bounds(q, kind, storage, dev_exp):
@@ -372,11 +376,12 @@ def test_batch_is_bitwise_identical_to_alone():
 # ------------------------------------------------------------ dense
 @pytest.mark.parametrize("storage,kind", [(lbm.STORE_F64, lbm.COLL_TRT),
                                           (lbm.STORE_F32, lbm.COLL_TRT),
-                                          (lbm.STORE_F64, lbm.COLL_MRT)])
+                                          (lbm.STORE_F64, lbm.COLL_MRT),
+                                          (lbm.STORE_F64, lbm.COLL_CM)])
 def test_dense_comparator_matches_oracle(storage, kind):
     lab = inputs.random_mask((15, 14, 13), 0.35, seed=8)
     per = 6
-    q = 19
+    q = 27 if kind == lbm.COLL_CM else 19
     coll, _, op = _params(q, kind, 0.8, (1e-5, 0, 0), [])
     ds = lbm.DenseSolver(lab, per, q, storage)
     ds.init()

@@ -48,14 +48,16 @@ def _states(q, n, seed):
 
 CASES = [(19, 1, 0.8, 0.0, 1.0), (19, 2, 0.7, 3 / 16, 1.0), (27, 1, 0.9, 0.0, 1.0),
          (27, 2, 0.6, 3 / 16, 1.0), (27, 3, 0.62, 0.0, 1.0), (27, 3, 0.8, 0.0, 1.3),
-         (27, 3, 1.0, 0.0, 1.0), (19, 4, 0.8, 0.0, 1.19), (19, 4, 0.55, 0.0, 1.6)]
-MRT_RATES = {0.8: (1.4, 1.4, 1.2, 1.98), 0.55: (1.1, 1.7, 0.6, 1.3)}
+         (27, 3, 1.0, 0.0, 1.0), (19, 4, 0.8, 0.0, 1.19), (19, 4, 0.55, 0.0, 1.6),
+         (27, 5, 0.7, 0.0, 1.2), (27, 5, 0.9, 0.0, 1.0)]
+RATES = {(4, 0.8): (1.4, 1.4, 1.2, 1.98), (4, 0.55): (1.1, 1.7, 0.6, 1.3),
+         (5, 0.7): (1.2, 0.8, 1.5, 1.9), (5, 0.9): (1.0, 1.0, 1.0, 1.0)}
 
 
 @pytest.mark.parametrize("q,kind,tau,magic,wb", CASES)
 def test_device_collision_matches_oracle(hostlib, q, kind, tau, magic, wb):
     F = (1e-5, -2e-6, 3e-6)
-    rates = MRT_RATES.get(tau, oracle.MRT_RATES) if kind == 4 else oracle.MRT_RATES
+    rates = RATES.get((kind, tau), oracle.MRT_RATES)
     p = oracle.params(q=q, kind=kind, tau=tau, magic=magic, omega_bulk=wb, force=F,
                       rates=rates)
     om1 = 1 / tau
