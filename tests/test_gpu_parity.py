@@ -397,15 +397,22 @@ def test_dense_comparator_matches_oracle(storage, kind):
 
 
 # -------------------------------------------------- full-size parity
-def test_full_size_packing_two_steps_fp32(packing256):
-    """256^3 packing at porosity 0.6, D3Q19 TRT FP32, in the benchmark's
-    launch configuration: one odd and one even step from a perturbed state
-    match the oracle's sparse AA scheme on every fluid cell."""
+@pytest.mark.parametrize("order,form", [(lbm.ORDER_MORTON, "int32"), (lbm.ORDER_BLOCKED, "runs")])
+def test_full_size_packing_two_steps_fp32(packing256, order, form):
+    """256^3 packing at porosity 0.6, D3Q19 TRT FP32: one odd and one even
+    step from a perturbed state match the oracle's sparse AA scheme on every
+    fluid cell -- in the benchmark's configuration (blocked order,
+    run-compressed index, default launch table) and with Morton order and
+    the int32 index."""
     lab, per, info, ref_lay = packing256
-    _say("full size two steps", info["n_fluid"])
+    _say("full size two steps", info["n_fluid"], order, form)
     q = 19
+    if order != lbm.ORDER_MORTON:
+        ref_lay = oracle.sparse_build(lab, per, q, order=order, align=64)
     coll, _, op = _params(q, lbm.COLL_TRT, 0.8, (1e-6, 0, 0), [])
-    dom = lbm.SparseDomain(lab, per, q)
+    dom = lbm.SparseDomain(lab, per, q, order)
+    if form == "runs":
+        dom.compact_runs()
     torch.cuda.synchronize()
     sol = lbm.Solver(dom, lbm.STORE_F32)
     f0 = _random_state(q, dom.n_fluid, seed=1, amp=1e-3)
@@ -759,7 +766,7 @@ def test_vessel_tree_full_size_two_steps():
     _say("vessel full size", info["n_fluid"], info["n_outlets"])
     coll, bs, op = _vessel_params()
     dom = lbm.SparseDomain(lab, per, 27, lbm.ORDER_BLOCKED)
-    dom.compact()
+    dom.compact_runs()            # the benchmark's index form
     torch.cuda.synchronize()
     sol = lbm.Solver(dom, lbm.STORE_F32)
     seen = _upload(sol, _random_state(27, dom.n_fluid, seed=2, amp=1e-3), 0)
