@@ -424,9 +424,11 @@ lbm_status lbm_compress_runs(const lbm_layout* L, const int32_t* index, void* ru
   lbm_status rc = check_layout(*L);
   if (rc) return rc;
   RunsView v = runs_view(*L, runs);
-  if (capacity < v.header)
+  if (capacity < v.header) {
+    *needed = v.header;
     return fail(LBM_ENOMEM, "runs buffer of %llu bytes is below the header size %llu",
                 (unsigned long long)capacity, (unsigned long long)v.header);
+  }
   hipStream_t st = (hipStream_t)stream;
   const uint32_t S = (uint32_t)L->stride;
   uint32_t total = 0;

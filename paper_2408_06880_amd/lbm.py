@@ -220,12 +220,13 @@ def lbm_runs_header_bytes(layout):
 
 def lbm_compress_runs(layout, index, runs, capacity, stream=None):
     """Returns (status, needed bytes): status 0 when the whole form was
-    written, LBM_ENOMEM when only the header fitted in `capacity`."""
+    written, LBM_ENOMEM when only the header fitted in `capacity`; raises
+    for any other error, including a capacity below the header size."""
     lib = load()
     need = _u64(0)
     rc = lib.lbm_compress_runs(ctypes.byref(layout), _ptr(index), _ptr(runs), int(capacity),
                                ctypes.byref(need), _stream(stream))
-    if rc not in (LBM_OK, LBM_ENOMEM) or (rc == LBM_ENOMEM and need.value == 0):
+    if rc != LBM_OK and (rc != LBM_ENOMEM or int(capacity) < lbm_runs_header_bytes(layout)):
         msg = lib.lbm_last_error()
         raise LbmError("lbm_compress_runs", rc, msg.decode() if msg else "")
     return int(rc), int(need.value)

@@ -104,6 +104,10 @@ def test_invalid_arguments_rejected_on_host():
     # a buffer below the header size is refused before any device work
     expect(lbm.LBM_ENOMEM, lbm.lbm_compress_runs, lay, 16, 16,
            lbm.lbm_runs_header_bytes(lay) - 1, 0)
+    need = ctypes.c_uint64(0)
+    rc = lbm.load().lbm_compress_runs(ctypes.byref(lay), ctypes.c_void_p(16),
+                                      ctypes.c_void_p(16), 0, ctypes.byref(need), None)
+    assert rc == lbm.LBM_ENOMEM and need.value == lbm.lbm_runs_header_bytes(lay)
 
 
 def test_batch_mismatch_rejected_on_host():
