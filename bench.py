@@ -148,9 +148,6 @@ def serving_leg(n_requests):
 def _steady_run(lbm, torch, dom, storage, dev_exp, coll, K, tol, cap, L):
     """Advance a fresh solve in rounds of K steps until the mean-momentum
     residual drops below tol (or cap); returns its figures."""
-    if args.pipelined:
-        b, x = lbm.lbm_get_launch(lbm.KERNEL_ODD, q, storage)
-        lbm.lbm_set_launch(lbm.KERNEL_ODD, q, storage, 256, x, 1)
     sol = lbm.Solver(dom, storage, dev_exp)
     sol.init()
     jx, res, t_gpu = [], float("nan"), 0.0
