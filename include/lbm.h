@@ -358,8 +358,10 @@ typedef struct {
                       /* persistent workgroups that load the next tile's       */
                       /* offsets during the current tile (same results)        */
   int32_t cells_per_thread; /* even kernel: 2 = two neighbouring cells per    */
-                      /* thread with 2-wide loads/stores; 0 or 1 = one cell     */
-                      /* (the only choice for the other kernels)              */
+                      /* thread with 2-wide loads/stores, used when every      */
+                      /* state of the launch has an even stride (one cell      */
+                      /* otherwise); 0 or 1 = one cell (the only choice for    */
+                      /* the other kernels)                                    */
 } lbm_launch;
 
 /* Set / get the launch configuration used for (kernel, q, storage) from

@@ -481,7 +481,11 @@ static lbm_status step_group(lbm_state* const* states, const lbm_collision* cons
     }
     // Odd steps run one launch (group) per index form, each form being a
     // kernel of its own; even steps never read indices.
-    const uint32_t cpt = (!odd && cfg.cells_per_thread == 2) ? 2 : 1;
+    // Two cells per thread need an even stride: the 2-wide accesses stay
+    // aligned and the second cell of the last pair is a padding slot.
+    bool even_strides = true;
+    for (int32_t j = 0; j < n; ++j) even_strides = even_strides && (states[j]->layout.stride % 2 == 0);
+    const uint32_t cpt = (!odd && cfg.cells_per_thread == 2 && even_strides) ? 2 : 1;
     for (int form = IDX_I32; form <= IDX_RUN; ++form) {
       int32_t j = 0;
       while (j < n) {

@@ -200,9 +200,10 @@ __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU))) void k_aa_step(const
 // 2-vector (cells k, k+1 of one direction block), twice the bytes per
 // memory instruction of the one-cell kernel.  v[j] holds slot j of both
 // cells; cell k's results replace the .x halves once collided (its inputs
-// are then dead), cell k+1's the .y halves.  When n_fluid is odd the last
-// pair's second cell is a padding slot (k+1 < stride): it collides its own
-// finite padding values, which only padding reads.
+// are then dead), cell k+1's the .y halves.  The host launches it only for
+// even strides, so the 2-wide accesses are aligned and, when n_fluid is
+// odd, the last pair's second cell is a padding slot (k+1 < stride): it
+// collides its own finite padding values, which only padding reads.
 template <int Q, int COLL, int ST>
 __global__ __launch_bounds__(256) void k_even_pair(const StepArgs a) {
   using SP = Store<ST>;

@@ -834,6 +834,13 @@ def test_even_kernel_two_cells_per_thread_is_bitwise_identical(q, kind, storage)
             lbm.lbm_set_launch(lbm.KERNEL_EVEN, q, storage, 256, 0, 0, cpt)
             doms = [lbm.SparseDomain(lab, 3, q, lbm.ORDER_BLOCKED),
                     lbm.SparseDomain(lab[:, :, 1:], 3, q, lbm.ORDER_BLOCKED)]
+            # an unpadded list with an odd stride falls back to one cell per
+            # thread (stepped alone below)
+            odd = lbm.SparseDomain(lab, 3, q, lbm.ORDER_BLOCKED, align=1)
+            assert odd.stride == odd.n_fluid and odd.stride % 2 == 1
+            so = lbm.Solver(odd, storage, dev_exp)
+            _upload(so, _random_state(q, odd.n_fluid, seed=9), dev_exp)
+            so.step(5, coll, bs)
             sols = []
             for j, d in enumerate(doms):
                 d.compact_runs()
@@ -845,7 +852,7 @@ def test_even_kernel_two_cells_per_thread_is_bitwise_identical(q, kind, storage)
             lbm.lbm_step_batch([s.state for s in sols], [coll, coll], [bs, bs], 5)
             torch.cuda.synchronize()
             out.append([s.pdf[:q * s.domain.stride].view(q, -1)[:, :s.domain.n_fluid].clone()
-                        for s in sols])
+                        for s in sols + [so]])
     finally:
         lbm.lbm_set_launch(lbm.KERNEL_EVEN, q, storage, *old)
     for a, b in zip(*out):
