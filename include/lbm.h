@@ -240,8 +240,9 @@ lbm_status lbm_compress_index(const lbm_layout* layout, const int32_t* index, vo
  *      If capacity >= *needed, writes it and returns LBM_OK; otherwise
  *      writes voff and mask only and returns LBM_ENOMEM: allocate *needed
  *      bytes and call again.  A capacity below the header size returns
- *      LBM_ENOMEM with *needed = the header size and writes nothing.  SYNC.  lbm_state.index stays required next to
- *      runs (moments at odd t and the pull step read it). */
+ *      LBM_ENOMEM with *needed = the header size and writes nothing.  SYNC.
+ *      lbm_state.index stays required next to runs (moments at odd t and
+ *      the pull step read it). */
 uint64_t lbm_runs_header_bytes(const lbm_layout* layout);
 lbm_status lbm_compress_runs(const lbm_layout* layout, const int32_t* index, void* runs,
                              uint64_t capacity, uint64_t* needed, void* stream);

@@ -10,8 +10,9 @@
 
 namespace lbm {
 
-// Run starts of direction i for the calling lane's entry p (k < S) of wave
-// w; lanes past the list end start nothing.
+// Whether the calling lane starts a run: lane 0 always does, a lane inside
+// the list does when its entry p is not its left neighbour's plus one, a
+// lane past the list end never does.
 __device__ __forceinline__ bool run_start(int32_t p, uint32_t lane, bool in_list) {
   const int32_t prev = __shfl_up(p, 1, (int)kRunWave);
   return lane == 0 || (in_list && p != prev + 1);
