@@ -430,6 +430,34 @@ def test_full_size_packing_two_steps_fp32(packing256, order, form):
         assert np.max(np.abs(got - ref) / ref) <= 1e-5
 
 
+@pytest.mark.parametrize("phi", [0.4, 0.95])
+def test_full_size_packing_other_porosities(phi):
+    """The benchmark's other 256^3 porosities (6.7 M and 15.9 M fluid cells)
+    in its configuration (blocked order, run-compressed index): one odd and
+    one even FP32 TRT step match the oracle's sparse AA scheme."""
+    lab, per, info = inputs.workload_c1(phi)
+    _say("full size", phi, info["n_fluid"])
+    q = 19
+    ref_lay = oracle.sparse_build(lab, per, q, order=lbm.ORDER_BLOCKED, align=64)
+    coll, _, op = _params(q, lbm.COLL_TRT, 0.8, (1e-6, 0, 0), [])
+    dom = lbm.SparseDomain(lab, per, q, lbm.ORDER_BLOCKED)
+    dom.compact_runs()
+    torch.cuda.synchronize()
+    assert dom.n_fluid == ref_lay.n_fluid == info["n_fluid"]
+    sol = lbm.Solver(dom, lbm.STORE_F32)
+    seen = _upload(sol, _random_state(q, dom.n_fluid, seed=3, amp=1e-3), 0)
+    pdf = np.zeros(q * ref_lay.stride)
+    for i in range(q):
+        pdf[i * ref_lay.stride:i * ref_lay.stride + dom.n_fluid] = seen[i]
+    for t in range(2):
+        sol.step(1, coll)
+        pdf = oracle.sparse_run(op, ref_lay, pdf, t, 1)
+        torch.cuda.synchronize()
+        got = _download(sol, 0)
+        ref = oracle.sparse_gather(ref_lay, pdf, t + 1)
+        assert np.max(np.abs(got - ref) / ref) <= 1e-5
+
+
 def test_empty_and_single_cell_domains():
     lab = np.ones((4, 4, 4), np.uint8)
     dom = lbm.SparseDomain(lab, 7, 19)
