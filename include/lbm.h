@@ -247,6 +247,18 @@ uint64_t lbm_runs_header_bytes(const lbm_layout* layout);
 lbm_status lbm_compress_runs(const lbm_layout* layout, const int32_t* index, void* runs,
                              uint64_t capacity, uint64_t* needed, void* stream);
 
+/* Change a state's storage format (the deviation storage of the FP16/BF16
+ * formats; no counterpart in the paper): every slot of src's PDF-list,
+ * padding included, is decoded to delta = f - w in FP64 and encoded in
+ * dst->storage (16-bit formats round to nearest even at dst->dev_exp);
+ * dst->t = src->t.  FP16/BF16/FP32 deviations convert to FP32-deviation or
+ * FP64 exactly.  The parity does not matter (opposite directions share a
+ * weight).  dst: a state of the same layout (q, stride, n_fluid) whose pdf
+ * holds q*stride elements of its storage and does not overlap src's; its
+ * index, index16, runs and links are not touched.  Errors: LBM_EINVAL,
+ * LBM_EDEVICE. */
+lbm_status lbm_convert(const lbm_state* src, lbm_state* dst, void* stream);
+
 /* Initialise every fluid cell to the equilibrium of (rho0, u0) and set
  * state->t = 0.  u0: host double[3].  Padding slots are zeroed (deviation)
  * or set to the weights.  Errors: LBM_EINVAL, LBM_EDEVICE. */

@@ -452,6 +452,30 @@ lbm_status lbm_compress_runs(const lbm_layout* L, const int32_t* index, void* ru
   return LBM_OK;
 }
 
+// ------------------------------------------------------ storage change
+lbm_status lbm_convert(const lbm_state* src, lbm_state* dst, void* stream) {
+  lbm_status rc = check_state(src);
+  if (rc) return rc;
+  if (!dst) return fail(LBM_EINVAL, "dst is NULL");
+  if (!storage_ok(dst->storage)) return fail(LBM_EINVAL, "unknown storage %d", dst->storage);
+  if (is16(dst->storage) && (dst->dev_exp < 0 || dst->dev_exp > 24))
+    return fail(LBM_EINVAL, "dev_exp must be in [0, 24] (got %d)", dst->dev_exp);
+  if (dst->layout.q != src->layout.q || dst->layout.stride != src->layout.stride ||
+      dst->layout.n_fluid != src->layout.n_fluid)
+    return fail(LBM_EINVAL, "src and dst layouts differ");
+  if (src->layout.stride > 0 && !dst->pdf) return fail(LBM_EINVAL, "dst pdf is NULL");
+  if (src->layout.stride > 0 && dst->pdf == src->pdf)
+    return fail(LBM_EINVAL, "src and dst must not share the PDF-list");
+  const int ea = is16(src->storage) ? src->dev_exp : 0;
+  const int eb = is16(dst->storage) ? dst->dev_exp : 0;
+  HIP_TRY(launch_convert(src->layout.q, src->storage, dst->storage, src->pdf, dst->pdf,
+                         (uint32_t)src->layout.stride, ldexpf(1.0f, -ea), ldexpf(1.0f, eb),
+                         (hipStream_t)stream),
+          "convert");
+  dst->t = src->t;
+  return LBM_OK;
+}
+
 // ---------------------------------------------------------- stepping
 lbm_status lbm_init_equilibrium(lbm_state* s, double rho0, const double* u0, void* stream) {
   lbm_status rc = check_state(s);

@@ -350,6 +350,67 @@ __global__ __launch_bounds__(256) void k_copy(const v4f* __restrict__ src, v4f* 
   if (i < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
+// Storage conversion: every slot decoded to its deviation delta = f - w in
+// FP64 and encoded in the destination format.  Opposite directions share
+// their weight, so the slot's population (natural or swapped, by the AA
+// parity) does not matter.
+template <int Q, int SA, int SB>
+__global__ __launch_bounds__(256) void k_convert(const void* src_, void* dst_, uint32_t S,
+                                                 float inv_scale_a, float scale_b) {
+  using A = Store<SA>;
+  using B = Store<SB>;
+  const typename A::T* src = static_cast<const typename A::T*>(src_);
+  typename B::T* dst = static_cast<typename B::T*>(dst_);
+  const uint64_t n = (uint64_t)Q * S;
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (uint64_t)gridDim.x * blockDim.x) {
+    int cx, cy, cz;
+    double w;
+    dir_of<Q>((int)(e / S), cx, cy, cz, w);
+    const double dev =
+        (double)A::load(src[e], typename A::R(w), typename A::R(inv_scale_a));
+    dst[e] = B::store(typename B::R(dev), typename B::R(w), typename B::R(scale_b));
+  }
+}
+
+template <int Q, int SA>
+static hipError_t launch_convert_a(int sb, const void* src, void* dst, uint32_t S,
+                                   float inv_scale_a, float scale_b, hipStream_t st) {
+  const uint64_t n = (uint64_t)Q * S;
+  uint64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks == 0) return hipSuccess;
+  const dim3 g((unsigned)blocks), b(256);
+  switch (sb) {
+    case ST_F64: hipLaunchKernelGGL((k_convert<Q, SA, ST_F64>), g, b, 0, st, src, dst, S, inv_scale_a, scale_b); break;
+    case ST_F32: hipLaunchKernelGGL((k_convert<Q, SA, ST_F32>), g, b, 0, st, src, dst, S, inv_scale_a, scale_b); break;
+    case ST_F16DEV: hipLaunchKernelGGL((k_convert<Q, SA, ST_F16DEV>), g, b, 0, st, src, dst, S, inv_scale_a, scale_b); break;
+    case ST_BF16DEV: hipLaunchKernelGGL((k_convert<Q, SA, ST_BF16DEV>), g, b, 0, st, src, dst, S, inv_scale_a, scale_b); break;
+    case ST_F32DEV: hipLaunchKernelGGL((k_convert<Q, SA, ST_F32DEV>), g, b, 0, st, src, dst, S, inv_scale_a, scale_b); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int Q>
+static hipError_t launch_convert_q(int sa, int sb, const void* src, void* dst, uint32_t S,
+                                   float inv_scale_a, float scale_b, hipStream_t st) {
+  switch (sa) {
+    case ST_F64: return launch_convert_a<Q, ST_F64>(sb, src, dst, S, inv_scale_a, scale_b, st);
+    case ST_F32: return launch_convert_a<Q, ST_F32>(sb, src, dst, S, inv_scale_a, scale_b, st);
+    case ST_F16DEV: return launch_convert_a<Q, ST_F16DEV>(sb, src, dst, S, inv_scale_a, scale_b, st);
+    case ST_BF16DEV: return launch_convert_a<Q, ST_BF16DEV>(sb, src, dst, S, inv_scale_a, scale_b, st);
+    case ST_F32DEV: return launch_convert_a<Q, ST_F32DEV>(sb, src, dst, S, inv_scale_a, scale_b, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_convert(int q, int sa, int sb, const void* src, void* dst, uint32_t S,
+                          float inv_scale_a, float scale_b, hipStream_t st) {
+  if (q == 19) return launch_convert_q<19>(sa, sb, src, dst, S, inv_scale_a, scale_b, st);
+  return launch_convert_q<27>(sa, sb, src, dst, S, inv_scale_a, scale_b, st);
+}
+
 hipError_t launch_copy(void* dst, const void* src, uint64_t bytes, hipStream_t st) {
   const uint64_t n = bytes / 16;
   if (n == 0) return hipSuccess;

@@ -42,6 +42,9 @@ constexpr int kRedBlock = 256;
 hipError_t launch_reduce(int q, int storage, const StepArgs& a, bool odd_t, double* partials,
                          double* out, hipStream_t st);
 hipError_t launch_copy(void* dst, const void* src, uint64_t bytes, hipStream_t st);
+// Storage conversion of a whole PDF-list (q * S slots), format sa -> sb.
+hipError_t launch_convert(int q, int sa, int sb, const void* src, void* dst, uint32_t S,
+                          float inv_scale_a, float scale_b, hipStream_t st);
 
 // builder.hip
 struct BuildArgs {

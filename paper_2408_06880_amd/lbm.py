@@ -106,6 +106,7 @@ _SIGS = {
     "lbm_runs_header_bytes": (_u64, [ctypes.POINTER(lbm_layout)]),
     "lbm_compress_runs": (_i32, [ctypes.POINTER(lbm_layout), _vp, _vp, _u64,
                                  ctypes.POINTER(_u64), _vp]),
+    "lbm_convert": (_i32, [ctypes.POINTER(lbm_state), ctypes.POINTER(lbm_state), _vp]),
     "lbm_init_equilibrium": (_i32, [ctypes.POINTER(lbm_state), _f64, ctypes.POINTER(_f64), _vp]),
     "lbm_step": (_i32, [ctypes.POINTER(lbm_state), _i32, ctypes.POINTER(lbm_collision),
                         ctypes.POINTER(lbm_bspec), _vp]),
@@ -230,6 +231,10 @@ def lbm_compress_runs(layout, index, runs, capacity, stream=None):
         msg = lib.lbm_last_error()
         raise LbmError("lbm_compress_runs", rc, msg.decode() if msg else "")
     return int(rc), int(need.value)
+
+
+def lbm_convert(src, dst, stream=None):
+    _call("lbm_convert", ctypes.byref(src), ctypes.byref(dst), _stream(stream))
 
 
 def lbm_init_equilibrium(state, rho0=1.0, u0=(0.0, 0.0, 0.0), stream=None):
@@ -462,6 +467,13 @@ class Solver:
 
     def step(self, n, coll, bs=None, stream=None):
         lbm_step(self.state, n, coll, bs, stream)
+
+    def converted(self, storage, dev_exp=0, stream=None):
+        """A new Solver on the same domain holding this state in `storage`
+        (same step count); this one is left unchanged."""
+        other = Solver(self.domain, storage, dev_exp, device=self.pdf.device)
+        lbm_convert(self.state, other.state, stream)
+        return other
 
     def step_pull(self, n, coll, bs=None, stream=None):
         """n (even) two-array pull steps; allocates the second array once."""

@@ -50,6 +50,7 @@ class Result:
     permeability: float = math.nan
     residual: float = math.nan
     converged: bool = False
+    refined_at: int = 0          # step at which the solve moved to finer storage
     error: str = ""
 
     @property
@@ -84,12 +85,16 @@ def percentile(xs, p):
 class Server:
     def __init__(self, stepper, budget_bytes, K=100, tol=1e-6, max_steps=200_000,
                  max_active=64, target_cells=None, clock=time.perf_counter, sleep=time.sleep,
-                 on_finish=None):
+                 on_finish=None, refine_tol=None):
         """target_cells: admit new solves only while the active fluid cells
         stay below this (one solve is always admitted).  Enough cells to
         saturate the GPU keep throughput, fewer concurrent solves finish
         sooner; None admits whatever the memory budget allows.  on_finish:
-        called with each Result as its request retires."""
+        called with each Result as its request retires.  refine_tol: once a
+        solve's residual drops below it, the stepper's refine() may move the
+        solve to finer storage (16-bit storage can stall near the steady
+        state when per-step changes fall below its resolution); the residual
+        history restarts and the solve then runs to tol."""
         if K <= 0 or K % 2:
             raise ValueError("K must be a positive even number of steps")
         self.stepper = stepper
@@ -102,6 +107,7 @@ class Server:
         self.clock = clock
         self.sleep = sleep
         self.on_finish = on_finish
+        self.refine_tol = refine_tol
 
     def run(self, trace):
         """Serve `trace` (list of Request) in real time; returns (results,
@@ -142,7 +148,7 @@ class Server:
                 res.admitted = self.clock() - t0
                 res.n_fluid = self.stepper.n_fluid(handle)
                 active.append({"req": r, "res": res, "handle": handle, "bytes": need,
-                               "jx": []})
+                               "jx": [], "refined": False})
                 used += need
             if not active:
                 if pending:
@@ -167,7 +173,15 @@ class Server:
                     done = True
                 elif len(a["jx"]) >= 2 and abs(a["jx"][-1]) > 0:
                     res.residual = abs(a["jx"][-1] - a["jx"][-2]) / abs(a["jx"][-1])
-                    if res.steps >= 2 * self.K and res.residual < self.tol:
+                    refined_now = False
+                    if (self.refine_tol is not None and not a["refined"] and
+                            res.steps >= 2 * self.K and res.residual < self.refine_tol):
+                        a["refined"] = True
+                        refined_now = bool(self.stepper.refine(a["handle"]))
+                        if refined_now:
+                            a["jx"] = []
+                            res.refined_at = res.steps
+                    if not refined_now and res.steps >= 2 * self.K and res.residual < self.tol:
                         res.converged = True
                         done = True
                 if res.steps >= self.max_steps:
@@ -213,6 +227,8 @@ class MockStepper:
     deterministically without a GPU."""
 
     def __init__(self, rate_flups=1e9, bytes_per_cell=112, decay=0.9, fail_rid=None):
+        """refine() halves a solve's step rate (finer storage moves twice the
+        bytes) and can be called once per solve."""
         self.rate = rate_flups
         self.bpc = bytes_per_cell
         self.decay = decay
@@ -246,9 +262,15 @@ class MockStepper:
         return h["nf"]
 
     def step(self, hs, n):
-        self.now += sum(h["nf"] for h in hs) * n / self.rate
+        self.now += sum(h["nf"] * (2 if h.get("fine") else 1) for h in hs) * n / self.rate
         for h in hs:
             h["t"] += n
+
+    def refine(self, h):
+        if h.get("fine"):
+            return False
+        h["fine"] = True
+        return True
 
     def reduce(self, hs):
         out = []
@@ -267,12 +289,18 @@ class GpuStepper:
     """liblbm backend: seeded packing -> GPU builder -> resident solve."""
 
     def __init__(self, storage=None, q=19, dev_exp=14, order=None, index="runs", magic=3 / 16,
-                 r_range=(4.0, 12.0), stream=None):
+                 r_range=(4.0, 12.0), stream=None, refine_storage=None):
+        """refine_storage: storage a solve moves to when the server asks
+        (lbm_convert, exact from 16-bit deviations); default FP32 deviations
+        for 16-bit storage, none otherwise."""
         from . import lbm
         self.lbm = lbm
         self.storage = lbm.STORE_F16DEV if storage is None else storage
         self.q = q
         self.dev_exp = dev_exp if self.storage == lbm.STORE_F16DEV else 0
+        if refine_storage is None and self.storage in (lbm.STORE_F16DEV, lbm.STORE_BF16DEV):
+            refine_storage = lbm.STORE_F32DEV
+        self.refine_storage = refine_storage
         self.order = lbm.ORDER_BLOCKED if order is None else order
         if index not in ("runs", "16", "32"):
             raise ValueError(f"index form must be 'runs', '16' or '32' (got {index!r})")
@@ -313,6 +341,8 @@ class GpuStepper:
             per_cell += (self.q - 1) * 2
         elif self.index == "runs":
             per_cell += (self.q - 1) * (8 / 64 + 4 / 4)
+        if self.refine_storage is not None:
+            per_cell += self.q * self.lbm.STORE_BYTES[self.refine_storage]
         return int(nf * per_cell) + (1 << 20)
 
     def build(self, r):
@@ -333,24 +363,45 @@ class GpuStepper:
     def n_fluid(self, h):
         return h["sol"].domain.n_fluid
 
+    def _by_storage(self, hs):
+        groups = {}
+        for j, h in enumerate(hs):
+            groups.setdefault(h["sol"].storage, []).append(j)
+        return groups.values()
+
     def step(self, hs, n):
-        self.lbm.lbm_step_batch([h["sol"].state for h in hs], [h["coll"] for h in hs], None, n,
-                                self.stream)
+        # one batch per storage format (refined solves run in finer storage)
+        for idx in self._by_storage(hs):
+            self.lbm.lbm_step_batch([hs[j]["sol"].state for j in idx],
+                                    [hs[j]["coll"] for j in idx], None, n, self.stream)
 
     def reduce(self, hs):
         need = sum(self.lbm.lbm_reduce_workspace_bytes(h["sol"].domain.layout) for h in hs)
         if self._ws is None or self._ws.numel() < need:
             self._ws = self.torch.empty(max(need, 1 << 16), dtype=self.torch.uint8, device="cuda")
-        red = self.lbm.lbm_reduce_batch([h["sol"].state for h in hs], [h["coll"] for h in hs],
-                                        self._ws, self.stream, check=False)
-        return [(r.mom[0], bool(r.finite)) for r in red]
+        out = [None] * len(hs)
+        for idx in self._by_storage(hs):
+            red = self.lbm.lbm_reduce_batch([hs[j]["sol"].state for j in idx],
+                                            [hs[j]["coll"] for j in idx], self._ws, self.stream,
+                                            check=False)
+            for j, r in zip(idx, red):
+                out[j] = (r.mom[0], bool(r.finite))
+        return out
+
+    def refine(self, h):
+        """Move a solve to the refine storage; False when it is there already."""
+        if self.refine_storage is None or h["sol"].storage == self.refine_storage:
+            return False
+        h["sol"] = h["sol"].converted(self.refine_storage, 0, stream=self.stream)
+        return True
 
     def free(self, h):
         h["sol"] = None
         h["coll"] = None
 
 
-def run_sequential(stepper, trace, K=100, tol=1e-6, max_steps=200_000):
+def run_sequential(stepper, trace, K=100, tol=1e-6, max_steps=200_000, refine_tol=None):
     """Baseline: the same trace served one solve at a time (no batching)."""
-    srv = Server(stepper, budget_bytes=1 << 62, K=K, tol=tol, max_steps=max_steps, max_active=1)
+    srv = Server(stepper, budget_bytes=1 << 62, K=K, tol=tol, max_steps=max_steps, max_active=1,
+                 refine_tol=refine_tol)
     return srv.run(trace)

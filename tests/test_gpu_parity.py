@@ -887,3 +887,35 @@ def test_even_kernel_two_cells_per_thread_is_bitwise_identical(q, kind, storage)
         d = (a.double() - b.double()).abs()
         bad = torch.nonzero(d)
         assert torch.equal(a, b), (float(d.max()), bad.shape[0], bad[:5].tolist())
+
+
+def test_convert_storage_formats():
+    """lbm_convert: FP16 deviations convert to FP32 deviations and FP64
+    exactly (value for value, at an odd step count, so in swapped slots),
+    FP64 -> FP16 gives back the same codes, the step count is kept, and the
+    converted state steps on (the serving tests check the accuracy of a
+    solve continued after conversion)."""
+    lab = inputs.random_mask((20, 17, 15), 0.3, seed=21)
+    dom = lbm.SparseDomain(lab, 7, 19, lbm.ORDER_BLOCKED)
+    q, S, nf = 19, dom.stride, dom.n_fluid
+    coll = lbm.collision(lbm.COLL_TRT, tau=0.8, force=(1e-5, 0, 0))
+    a = lbm.Solver(dom, lbm.STORE_F16DEV, 14)
+    _upload(a, _random_state(q, nf, seed=5, amp=1e-2), 14)
+    a.step(3, coll)                                   # odd t: swapped slots
+    b = a.converted(lbm.STORE_F32DEV)
+    c = a.converted(lbm.STORE_F64)
+    torch.cuda.synchronize()
+    assert b.t == c.t == a.t == 3
+    da = _download(a, 14)
+    assert np.array_equal(_download(b, 0), da) and np.array_equal(_download(c, 0), da)
+    # FP64 -> FP16 rounds to the nearest code, as the host codec does
+    d = c.converted(lbm.STORE_F16DEV, 14)
+    torch.cuda.synchronize()
+    assert torch.equal(d.pdf[:q * S].view(q, S)[:, :nf], a.pdf[:q * S].view(q, S)[:, :nf])
+    b.step(1, coll)
+    r = b.reduce(coll)
+    assert b.t == 4 and r.finite and abs(r.mass - a.reduce(coll).mass) < 1e-5 * r.mass
+    # layouts must match
+    other = lbm.SparseDomain(lab[:, :, 1:], 7, 19, lbm.ORDER_BLOCKED)
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_convert(a.state, lbm.Solver(other, lbm.STORE_F32).state)

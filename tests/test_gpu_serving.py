@@ -82,3 +82,32 @@ def test_tuner_installs_a_measured_configuration(tmp_path):
     finally:
         for k, cfg in zip((0, 1), old):
             lbm.lbm_set_launch(k, 19, lbm.STORE_F32, *cfg)
+
+
+def test_refinement_reaches_fp32_accuracy_and_stays_batch_independent():
+    """FP16-deviation solves moved to FP32 deviations once their residual is
+    below 1e-5 (lbm_convert, exact): the served permeability then has the
+    FP32 error against the FP64 oracle, and batched results still equal the
+    solves alone."""
+    req = server.Request(rid=0, arrival=0.0, L=24, phi=0.55, seed=77, tau=0.8, force=1e-6)
+    res, _ = server.Server(server.GpuStepper(storage=lbm.STORE_F16DEV), 1 << 34, K=100,
+                           tol=1e-6, max_steps=8000, refine_tol=1e-5).run([req])
+    r = res[0]
+    assert r.converged and 0 < r.refined_at < r.steps
+    lab, info = inputs.boolean_spheres(24, 4.0, 12.0, 0.55, seed=77)
+    p = oracle.params(q=19, kind=oracle.TRT, tau=0.8, magic=3 / 16, force=(1e-6, 0, 0))
+    A = oracle.dense_run(p, lab, inputs.PERIODIC_ALL, r.steps, oracle.dense_init(19, lab))
+    _, J, nf = oracle.dense_reduce(p, lab, A)
+    k_ref = (0.8 - 0.5) / 3.0 * (J[0] / 24 ** 3) / 1e-6
+    err = abs(r.permeability - k_ref) / abs(k_ref)
+    print(f"[gpu-test] refined at {r.refined_at}, steps {r.steps}, rel err {err:.2e}", flush=True)
+    assert err < 5e-5
+    trace = _trace()
+    mixed, _ = server.Server(server.GpuStepper(storage=lbm.STORE_F16DEV), 1 << 34, K=100,
+                             tol=1e-6, max_steps=3000, refine_tol=1e-4).run(trace)
+    alone, _ = server.run_sequential(server.GpuStepper(storage=lbm.STORE_F16DEV), _trace(),
+                                     K=100, tol=1e-6, max_steps=3000, refine_tol=1e-4)
+    assert any(a.refined_at for a in mixed)
+    for a, b in zip(mixed, alone):
+        assert (a.steps, a.refined_at, a.converged) == (b.steps, b.refined_at, b.converged)
+        assert a.permeability == b.permeability

@@ -117,3 +117,34 @@ def test_target_cells_limits_concurrency_and_cuts_median_latency():
         assert met["completed"] == 30
         lat[tgt] = met["p50_latency_s"]
     assert lat[2 * 96 ** 3] < lat[None]
+
+
+def test_refinement_moves_solves_to_finer_storage_once():
+    """With refine_tol, a solve whose residual drops below it is moved to
+    finer storage once, its residual history restarts, and it then runs to
+    tol; without refine_tol nothing is refined."""
+    trace = server.make_trace(6, 50.0, seed=5, L_range=(16, 32))
+    for tol_r in (None, 1e-3):
+        st = server.MockStepper(rate_flups=1e8, decay=0.8)
+        res, met = server.Server(st, 1 << 40, K=100, tol=1e-6, max_steps=100_000,
+                                 clock=st.clock, sleep=st.sleep, refine_tol=tol_r).run(trace)
+        assert met["completed"] == 6 and all(r.converged for r in res)
+        for r in res:
+            if tol_r is None:
+                assert r.refined_at == 0
+            else:
+                # refined once, strictly before the end, and at least two more
+                # rounds ran to rebuild the residual in the finer storage
+                assert 0 < r.refined_at <= r.steps - 200
+
+
+def test_refinement_falls_back_when_the_stepper_cannot_refine():
+    class NoRefine(server.MockStepper):
+        def refine(self, h):
+            return False
+
+    trace = server.make_trace(3, 50.0, seed=2, L_range=(16, 24))
+    st = NoRefine(rate_flups=1e8, decay=0.8)
+    res, met = server.Server(st, 1 << 40, K=100, tol=1e-6, max_steps=100_000, clock=st.clock,
+                             sleep=st.sleep, refine_tol=1e-3).run(trace)
+    assert all(r.converged and r.refined_at == 0 for r in res)
