@@ -458,6 +458,36 @@ def test_full_size_packing_other_porosities(phi):
         assert np.max(np.abs(got - ref) / ref) <= 1e-5
 
 
+def test_full_size_384_packing_two_steps():
+    """The 384^3 mixed-precision geometry (34 M fluid cells, the largest
+    configuration) in the benchmark's configuration: one odd and one even
+    FP32 TRT step against the oracle's sparse AA scheme, every fluid cell."""
+    lab, info = inputs.boolean_spheres(384, 4.0, 12.0, 0.6, seed=21)
+    per = inputs.PERIODIC_ALL
+    _say("full size 384", info["n_fluid"])
+    q = 19
+    ref_lay = oracle.sparse_build(lab, per, q, order=lbm.ORDER_BLOCKED, align=64)
+    coll, _, op = _params(q, lbm.COLL_TRT, 0.8, (1e-6, 0, 0), [])
+    dom = lbm.SparseDomain(lab, per, q, lbm.ORDER_BLOCKED)
+    dom.compact_runs()
+    torch.cuda.synchronize()
+    assert dom.n_fluid == ref_lay.n_fluid == info["n_fluid"]
+    sol = lbm.Solver(dom, lbm.STORE_F32)
+    seen = _upload(sol, _random_state(q, dom.n_fluid, seed=4, amp=1e-3), 0)
+    pdf = np.zeros(q * ref_lay.stride)
+    for i in range(q):
+        pdf[i * ref_lay.stride:i * ref_lay.stride + dom.n_fluid] = seen[i]
+    del seen
+    for t in range(2):
+        sol.step(1, coll)
+        pdf = oracle.sparse_run(op, ref_lay, pdf, t, 1)
+        torch.cuda.synchronize()
+        got = _download(sol, 0)
+        ref = oracle.sparse_gather(ref_lay, pdf, t + 1)
+        assert np.max(np.abs(got - ref) / ref) <= 1e-5
+        del got, ref
+
+
 def test_empty_and_single_cell_domains():
     lab = np.ones((4, 4, 4), np.uint8)
     dom = lbm.SparseDomain(lab, 7, 19)
