@@ -37,14 +37,6 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def bytes_per_flup(q, b_pdf, b_idx=4):
-    """Algorithmic bytes per fluid-cell update (GPU access table of the
-    paper's AA section, generalised to the storage width)."""
-    odd = 2 * q * b_pdf + (q - 1) * b_idx
-    even = 2 * q * b_pdf
-    return odd, even, 0.5 * (odd + even)
-
-
 def copy_bandwidth(lbm, torch, nbytes=2 << 30, reps=10):
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
@@ -118,6 +110,88 @@ def recorded_traffic(workload_key):
         if kv.get("traffic_workload") == workload_key and kv.get("traffic_source_hash") == h:
             return float(kv["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
     return None, None
+
+
+def _device_used(torch):
+    """Device bytes in use (hipMemGetInfo), after returning cached blocks."""
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free, total = torch.cuda.mem_get_info()
+    return total - free
+
+
+def memory_study(L=256, phis=(0.2, 0.4, 0.6, 0.8, 0.95), storages=("f64", "f32", "f16dev")):
+    """Device memory of one D3Q19 solve against porosity: sparse AA with the
+    int32 index-list, sparse AA with only the run form, and the dense AA
+    comparator, each with density and velocity output fields.  Measured as
+    the drop of free device memory, next to the paper's memory model
+    (in-place AA on both sides, five other fields) and to the exact sum of
+    the buffers this library allocates."""
+    import torch
+
+    from paper_2408_06880_amd import costmodel, inputs, lbm
+    q = 19
+    rows = []
+    for phi in phis:
+        lab, per, info = inputs.workload_c1(phi, L=L)
+        lab_dev = torch.from_numpy(lab).cuda()
+        N = lab.size
+        for name in storages:
+            storage = {"f64": lbm.STORE_F64, "f32": lbm.STORE_F32,
+                       "f16dev": lbm.STORE_F16DEV}[name]
+            b = lbm.STORE_BYTES[storage]
+            fdt = torch.float64 if storage == lbm.STORE_F64 else torch.float32
+            bf = 8 if storage == lbm.STORE_F64 else 4
+            row = {"phi": round(info["phi"], 4), "storage": name}
+            for form in ("int32", "runs", "dense"):
+                base = _device_used(torch)
+                torch.cuda.reset_peak_memory_stats()
+                a0 = torch.cuda.memory_allocated()
+                if form == "dense":
+                    obj = lbm.DenseSolver(lab_dev, per, q, storage)
+                    n = N
+                    exact = obj.pdf.numel() * b + obj.mask.numel() * 4
+                else:
+                    dom = lbm.SparseDomain(lab_dev, per, q, lbm.ORDER_BLOCKED, 64)
+                    if form == "runs":
+                        dom.compact_runs(drop_index=True)
+                        # hand the int32 list's segment back to the device;
+                        # otherwise torch's cache carves the later buffers
+                        # out of it and holds the rest
+                        torch.cuda.synchronize()
+                        torch.cuda.empty_cache()
+                    obj = lbm.Solver(dom, storage, 14 if storage == lbm.STORE_F16DEV else 0)
+                    n = dom.stride
+                    nf = dom.n_fluid
+                    exact = dom.device_bytes() + obj.device_bytes()
+                fields = (torch.empty(n, dtype=fdt, device="cuda"),
+                          torch.empty(3 * n, dtype=fdt, device="cuda"))
+                exact += 4 * n * bf
+                peak = torch.cuda.max_memory_allocated() - a0
+                used = _device_used(torch) - base
+                row[form] = {"measured_bytes": used, "exact_bytes": exact,
+                             "build_peak_bytes": peak,
+                             "measured_per_fluid_cell": round(used / nf, 2)}
+                del obj, fields
+                if form != "dense":
+                    del dom
+            row["n_fluid"] = nf
+            row["model_sparse_aa"] = costmodel.memory(N, nf / N, q, b, 4, "aa", True)
+            row["model_dense_aa"] = costmodel.memory(N, nf / N, q, b, 4, "aa", False)
+            d = row["dense"]["measured_bytes"]
+            for form in ("int32", "runs"):
+                m = row[form]["measured_bytes"]
+                row[form]["vs_dense"] = round(m / d, 4)
+                # porosity at which this structure would match the dense one
+                row[form]["break_even_phi"] = round(d / (N * m / nf), 4)
+            row["int32_vs_model"] = round(row["int32"]["measured_bytes"] / row["model_sparse_aa"], 4)
+            row["dense_vs_model"] = round(d / row["model_dense_aa"], 4)
+            log(f"memory phi={row['phi']} {name}: int32 {row['int32']['measured_bytes'] / 2**20:.0f} "
+                f"MiB, runs {row['runs']['measured_bytes'] / 2**20:.0f} MiB, dense "
+                f"{d / 2**20:.0f} MiB")
+            rows.append(row)
+        del lab_dev
+    return rows
 
 
 def serving_leg(n_requests):
@@ -249,7 +323,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="packing",
-                    choices=["packing", "vessel", "mixed", "serving"],
+                    choices=["packing", "vessel", "mixed", "serving", "memory"],
                     help="packing: D3Q19 TRT 256^3 sphere packing (the metric's workload); "
                          "vessel: D3Q27 cumulant 512^3 vessel tree with inlet/outlets")
     ap.add_argument("--phi", type=float, default=0.6)
@@ -292,7 +366,16 @@ def main():
 
     import torch
 
-    from paper_2408_06880_amd import inputs, lbm
+    from paper_2408_06880_amd import costmodel, inputs, lbm
+
+    if args.workload == "memory":
+        print(json.dumps({"metric": "device memory per solve vs porosity, sparse AA (int32 "
+                                    "index-list or run form only) vs dense AA, D3Q19",
+                          "n_gpus": 1, "data": "synthetic",
+                          "config": {"workload": f"{args.L}^3 overlapping-sphere packings "
+                                                 "(r 4-12), density and velocity fields included"},
+                          "memory": memory_study(L=args.L)}), flush=True)
+        return
 
     if args.workload == "serving":
         from paper_2408_06880_amd import server
@@ -429,12 +512,12 @@ def main():
     b_pdf = lbm.STORE_BYTES[storage]
     # Algorithmic bytes of the method (int32 index-list): the figures the
     # roofline and the percentages are stated in.
-    b_odd_m, b_even_m, b_alg_m = bytes_per_flup(q, b_pdf, 4)
+    b_odd_m, b_even_m, b_alg_m = costmodel.aa_step_bytes(q, b_pdf, 4)
     if args.scheme == "pull":
         b_even_m = b_alg_m = b_odd_m
     # Bytes the index form in use actually needs (fewer for compressed forms).
     b_idx = 2 if index_form == "compact16" else 4
-    b_odd, b_even, b_alg = bytes_per_flup(q, b_pdf, b_idx)
+    b_odd, b_even, b_alg = costmodel.aa_step_bytes(q, b_pdf, b_idx)
     if index_form == "compact16":
         # one int32 base per direction per 256 cells; escaped entries also
         # read their int32 position

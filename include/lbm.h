@@ -142,7 +142,8 @@ typedef struct {
   int32_t storage;       /* LBM_STORE_*                                        */
   int32_t dev_exp;       /* 16-bit formats: stored = (f - w) * 2^dev_exp, 0..24 */
   void* pdf;             /* device, q*stride elements of the storage type      */
-  const int32_t* index;  /* device, (q-1)*stride (from lbm_build_sparse)       */
+  const int32_t* index;  /* device, (q-1)*stride (from lbm_build_sparse); may  */
+                         /* be NULL when runs is set (then no pull steps)      */
   const void* index16;   /* device, compact index-list (lbm_compress_index) of  */
                          /* the same index, or NULL; when set, index reads use  */
                          /* it and fall back to `index` for escaped entries     */
@@ -241,8 +242,9 @@ lbm_status lbm_compress_index(const lbm_layout* layout, const int32_t* index, vo
  *      writes voff and mask only and returns LBM_ENOMEM: allocate *needed
  *      bytes and call again.  A capacity below the header size returns
  *      LBM_ENOMEM with *needed = the header size and writes nothing.  SYNC.
- *      lbm_state.index stays required next to runs (moments at odd t and
- *      the pull step read it). */
+ *      A state with runs may drop its int32 index (lbm_state.index = NULL):
+ *      steps, moments and reductions then read only the run form; pull
+ *      steps still need the int32 index. */
 uint64_t lbm_runs_header_bytes(const lbm_layout* layout);
 lbm_status lbm_compress_runs(const lbm_layout* layout, const int32_t* index, void* runs,
                              uint64_t capacity, uint64_t* needed, void* stream);

@@ -91,8 +91,11 @@ lbm_status check_state(const lbm_state* s) {
   if (!storage_ok(s->storage)) return fail(LBM_EINVAL, "unknown storage %d", s->storage);
   if (is16(s->storage) && (s->dev_exp < 0 || s->dev_exp > 24))
     return fail(LBM_EINVAL, "dev_exp must be in [0, 24] (got %d)", s->dev_exp);
-  if (s->layout.n_fluid > 0 && (!s->pdf || !s->index))
-    return fail(LBM_EINVAL, "state pdf/index pointer is NULL");
+  if (s->layout.n_fluid > 0 && !s->pdf) return fail(LBM_EINVAL, "state pdf pointer is NULL");
+  if (s->layout.n_fluid > 0 && !s->index && !s->runs)
+    return fail(LBM_EINVAL, "state needs an index-list (index or runs)");
+  if (s->index16 && !s->index)
+    return fail(LBM_EINVAL, "the compact index-list needs the int32 one for escaped entries");
   if (s->layout.n_links > 0 && !s->links)
     return fail(LBM_EINVAL, "state has %lld links but links is NULL", (long long)s->layout.n_links);
   if (s->t < 0) return fail(LBM_EINVAL, "state.t is negative");
@@ -564,6 +567,8 @@ lbm_status lbm_step_pull(lbm_state* s, void** spare, int32_t n_steps, const lbm_
   hipStream_t st = (hipStream_t)stream;
   const lbm_launch cfg = get_cfg(LBM_KERNEL_ODD, s->layout.q, s->storage);
   // the pull kernel reads the compact or the int32 index-list
+  if (s->layout.n_fluid > 0 && !s->index)
+    return fail(LBM_EINVAL, "pull steps need the int32 index-list");
   const int idx = s->index16 ? IDX_16 : IDX_I32;
   for (int32_t step = 0; step < n_steps; ++step) {
     rc = link_update(s, bs, st);

@@ -136,6 +136,20 @@ hipError_t launch_links(int storage, const LinkArgs& a, hipStream_t st) {
 }
 
 // ----------------------------------------------------------- moments
+// Pull position of population i of cell k from the run-compressed
+// index-list, decoded by one thread alone: the value of the run holding
+// lane k % 64 (lane 0 always starts a run) plus the lane.  The step kernel
+// decodes runs a whole wave at a time instead.
+__device__ __forceinline__ uint32_t run_pos(const Seg& g, int q, int i, uint32_t k) {
+  const uint32_t w = k / kRunWave, lane = k % kRunWave;
+  const uint64_t* mk = g.rmask + (size_t)w * (q - 1);
+  uint32_t vb = g.rvoff[w];
+  for (int d = 1; d < i; ++d) vb += (uint32_t)__popcll(mk[d - 1]);
+  const uint64_t upto = lane == kRunWave - 1 ? ~0ull : ((2ull << lane) - 1ull);
+  const uint32_t r = (uint32_t)__popcll(mk[i - 1] & upto) - 1u;
+  return (uint32_t)(g.rval[vb + r] + (int32_t)lane);
+}
+
 // Post-collision deviations of cell k at the current time in natural order.
 // Even t: natural slots.  Odd t: population j sits where the cell pulled
 // population opp(j) from in the last (odd) step.
@@ -152,8 +166,9 @@ __device__ __forceinline__ void gather_post(const Seg& g, uint32_t k,
   for (int j = 0; j < Q; ++j) {
     uint32_t pos;
     if (ODD_T && j > 0)
-      pos = g.off16 ? pos16(g, Q, opp(j), j, k, t16)
-                    : (uint32_t)g.idx[(size_t)(opp(j) - 1) * g.S + k];
+      pos = g.rval    ? run_pos(g, Q, opp(j), k)
+            : g.off16 ? pos16(g, Q, opp(j), j, k, t16)
+                      : (uint32_t)g.idx[(size_t)(opp(j) - 1) * g.S + k];
     else
       pos = (uint32_t)j * g.S + k;
     d[j] = SP::load(pdf[pos], R(Lattice<Q>::w(j)), isc);

@@ -398,6 +398,8 @@ class SparseDomain:
         """Build the compact (16-bit) index-list next to the int32 one;
         returns the fraction of entries that escape to the int32 form."""
         import torch
+        if self.index is None:
+            raise ValueError("the int32 index-list was dropped; the compact form needs it")
         buf = torch.empty(max(lbm_index16_bytes(self.layout), 1), dtype=torch.uint8,
                           device=self.index.device)
         n_esc = lbm_compress_index(self.layout, self.index, buf, stream)
@@ -405,10 +407,20 @@ class SparseDomain:
         self.escaped = n_esc
         return n_esc / max((self.q - 1) * self.n_fluid, 1)
 
-    def compact_runs(self, stream=None):
+    def compact_runs(self, stream=None, drop_index=False):
         """Build the run-compressed index-list next to the int32 one (odd
-        steps then read it); returns its size in bytes per fluid cell."""
+        steps then read it); returns its size in bytes per fluid cell.
+
+        drop_index frees the int32 index-list afterwards: AA steps, moments
+        and reductions need only the run form, pull steps and the compact
+        16-bit form need the int32 one.  The freed buffer goes back to
+        torch's caching allocator (torch.cuda.empty_cache() hands it back
+        to the device)."""
         import torch
+        if self.index is None:
+            raise ValueError("the int32 index-list was dropped already")
+        if drop_index and self.index16 is not None:
+            raise ValueError("the compact index-list needs the int32 one; cannot drop it")
         dev = self.index.device
         hdr = lbm_runs_header_bytes(self.layout)
         buf = torch.empty(max(hdr, 1), dtype=torch.uint8, device=dev)
@@ -420,7 +432,14 @@ class SparseDomain:
                 raise LbmError("lbm_compress_runs", rc, "size changed between calls")
         self.runs = buf
         self.runs_bytes = need
+        if drop_index:
+            self.index = None   # lbm_compress_runs returned after its kernels ended
         return need / max(self.n_fluid, 1)
+
+    def device_bytes(self):
+        """Bytes of the device buffers this domain holds."""
+        bufs = (self.cells, self.index, self.links, self.index16, self.runs)
+        return sum(b.numel() * b.element_size() for b in bufs if b is not None)
 
     @property
     def n_fluid(self):
@@ -448,7 +467,7 @@ class Solver:
         st.storage = storage
         st.dev_exp = dev_exp
         st.pdf = self.pdf.data_ptr()
-        st.index = domain.index.data_ptr()
+        st.index = domain.index.data_ptr() if domain.index is not None else None
         st.index16 = domain.index16.data_ptr() if domain.index16 is not None else None
         st.runs = domain.runs.data_ptr() if domain.runs is not None else None
         st.links = domain.links.data_ptr() if domain.n_links else None
@@ -495,6 +514,11 @@ class Solver:
 
     def reduce(self, coll, stream=None, check=True):
         return lbm_reduce(self.state, coll, self._red_ws, stream, check)
+
+    def device_bytes(self):
+        """Bytes of the device buffers this solver holds (not the domain's)."""
+        bufs = (self.pdf, self._red_ws, getattr(self, "_spare", None))
+        return sum(b.numel() * b.element_size() for b in bufs if b is not None)
 
 
 class DenseSolver:

@@ -131,12 +131,14 @@ class Server:
             while queue and len(active) < self.max_active:
                 r = queue[0]
                 need = self.stepper.bytes_needed(r)
-                if need > self.budget:
+                # memory held only while the solve is built
+                extra = getattr(self.stepper, "transient_bytes", lambda _r: 0)(r)
+                if need + extra > self.budget:
                     queue.popleft()
-                    results[r.rid].error = f"needs {need} bytes > budget {self.budget}"
+                    results[r.rid].error = f"needs {need + extra} bytes > budget {self.budget}"
                     results[r.rid].finished = self.clock() - t0
                     continue
-                if used + need > self.budget:
+                if used + need + extra > self.budget:
                     break
                 if (self.target_cells is not None and active and
                         sum(a["res"].n_fluid for a in active) +
@@ -329,21 +331,37 @@ class GpuStepper:
         if r.rid not in self._labels:
             self._labels[r.rid] = self._pool.submit(self._geometry, r)
 
+    def _nf_bound(self, r):
+        return int(math.ceil(r.phi * r.L ** 3 * 1.02)) + 64
+
     def bytes_needed(self, r):
-        """PDF-list, int32 index-list and its compressed form, reduction
-        workspace, a little slack for the fluid list; from the target
-        porosity.  The run form is sized for one run start in four entries
-        (packings measure about one in twelve)."""
-        nf = int(math.ceil(r.phi * r.L ** 3 * 1.02)) + 64
+        """Device bytes a solve holds while it runs, from the target
+        porosity: PDF-list (plus the refine storage's, both held while
+        converting), index-list forms, fluid list, a little slack for the
+        reduction workspace.  The run form is sized for one run start in
+        four entries (packings measure about one in twelve); the int32
+        index-list is dropped once the run form is built."""
+        nf = self._nf_bound(r)
         b = self.lbm.STORE_BYTES[self.storage]
-        per_cell = self.q * b + (self.q - 1) * 4 + 4
+        per_cell = self.q * b + 4
         if self.index == "16":
-            per_cell += (self.q - 1) * 2
+            per_cell += (self.q - 1) * (4 + 2)
         elif self.index == "runs":
             per_cell += (self.q - 1) * (8 / 64 + 4 / 4)
+        else:
+            per_cell += (self.q - 1) * 4
         if self.refine_storage is not None:
             per_cell += self.q * self.lbm.STORE_BYTES[self.refine_storage]
         return int(nf * per_cell) + (1 << 20)
+
+    def transient_bytes(self, r):
+        """Bytes held only while a solve is built: the labels and the
+        builder's workspace (5 B per box cell) and, for the run form, the
+        int32 index-list it is compressed from."""
+        extra = 5 * r.L ** 3
+        if self.index == "runs":
+            extra += (self.q - 1) * 4 * self._nf_bound(r)
+        return extra
 
     def build(self, r):
         from .inputs import PERIODIC_ALL
@@ -353,7 +371,7 @@ class GpuStepper:
         if self.index == "16":
             dom.compact(stream=self.stream)
         elif self.index == "runs":
-            dom.compact_runs(stream=self.stream)
+            dom.compact_runs(stream=self.stream, drop_index=True)
         sol = self.lbm.Solver(dom, self.storage, self.dev_exp)
         sol.init(stream=self.stream)
         coll = self.lbm.collision(self.lbm.COLL_TRT, tau=r.tau, magic=self.magic,

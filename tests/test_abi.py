@@ -104,6 +104,19 @@ def test_invalid_arguments_rejected_on_host():
     # a buffer below the header size is refused before any device work
     expect(lbm.LBM_ENOMEM, lbm.lbm_compress_runs, lay, 16, 16,
            lbm.lbm_runs_header_bytes(lay) - 1, 0)
+    # an index-list is required: int32 or runs; the compact form needs int32
+    st = _fake_state()
+    st.index = None
+    expect(lbm.LBM_EINVAL, lbm.lbm_step, st, 1, lbm.collision(), None, 0)
+    st.index16 = 16
+    st.runs = 16
+    expect(lbm.LBM_EINVAL, lbm.lbm_step, st, 1, lbm.collision(), None, 0)
+    # runs without int32: AA steps may run, pull steps may not
+    st.index16 = None
+    spare = ctypes.c_void_p(32)
+    rc = lbm.load().lbm_step_pull(ctypes.byref(st), ctypes.byref(spare), 2,
+                                  ctypes.byref(lbm.collision()), None, None)
+    assert rc == lbm.LBM_EINVAL and b"int32" in lbm.load().lbm_last_error()
     need = ctypes.c_uint64(0)
     rc = lbm.load().lbm_compress_runs(ctypes.byref(lay), ctypes.c_void_p(16),
                                       ctypes.c_void_p(16), 0, ctypes.byref(need), None)

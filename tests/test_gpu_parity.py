@@ -688,6 +688,53 @@ def test_runs_steps_bitwise_equal_to_int32(q, kind, storage):
         assert (xa.mass, tuple(xa.mom)) == (xb.mass, tuple(xb.mom))
 
 
+@pytest.mark.parametrize("q,kind,storage,align", [(19, lbm.COLL_TRT, lbm.STORE_F32, 8),
+                                                  (27, lbm.COLL_CUMULANT, lbm.STORE_F64, 64),
+                                                  (19, lbm.COLL_MRT, lbm.STORE_BF16DEV, 1)])
+def test_runs_without_int32_index(q, kind, storage, align):
+    """With the int32 index-list freed after the run form is built, steps,
+    moments at odd and even t (decoded one thread at a time) and reductions
+    are bitwise those of the int32 path; strides that are not multiples of
+    64 leave a partial last wave.  Pull steps and the compact form refuse
+    the state."""
+    lab = inputs.random_mask((29, 27, 25), 0.3, seed=11, n_classes=3, class_fraction=0.5)
+    coll, bs, _ = _params(q, kind, 0.7, (1e-5, 0, 0), CLASSES)
+    d32 = lbm.SparseDomain(lab, 3, q, lbm.ORDER_BLOCKED, align=align)
+    dr = lbm.SparseDomain(lab, 3, q, lbm.ORDER_BLOCKED, align=align)
+    held = dr.device_bytes()
+    dr.compact_runs(drop_index=True)
+    torch.cuda.synchronize()
+    assert dr.index is None
+    assert dr.device_bytes() == held - d32.index.numel() * 4 + dr.runs.numel()
+    dev_exp = 14 if storage == lbm.STORE_F16DEV else 0
+    a = lbm.Solver(d32, storage, dev_exp)
+    b = lbm.Solver(dr, storage, dev_exp)
+    assert b.state.index is None
+    a.init()
+    b.init()
+    nf = d32.n_fluid
+    for n in (1, 1, 7, 1):
+        a.step(n, coll, bs)
+        b.step(n, coll, bs)
+        torch.cuda.synchronize()
+        assert torch.equal(a.pdf, b.pdf)
+        for f64 in (True, False):
+            ra, ua = a.moments(coll, f64)
+            rb, ub = b.moments(coll, f64)
+            assert torch.equal(ra[:nf], rb[:nf]) and torch.equal(ua[:, :nf], ub[:, :nf])
+        xa, xb = a.reduce(coll), b.reduce(coll)
+        assert (xa.mass, tuple(xa.mom)) == (xb.mass, tuple(xb.mom))
+    with pytest.raises(lbm.LbmError):
+        b.step_pull(2, coll, bs)
+    with pytest.raises(ValueError):
+        dr.compact()
+    # the pull error left the state as it was
+    a.step(1, coll, bs)
+    b.step(1, coll, bs)
+    torch.cuda.synchronize()
+    assert torch.equal(a.pdf, b.pdf)
+
+
 def test_runs_batch_mixes_index_forms():
     """One batch holding int32, compact and run-form solves (one launch per
     form on odd steps) gives each solve the PDFs it gets alone."""
