@@ -127,8 +127,13 @@ class Server:
                 queue.append(r)
                 results[r.rid] = Result(rid=r.rid, arrival=r.arrival)
                 self.stepper.prepare(r)   # host-side set-up may start now
-            # admission: FIFO while the head fits the memory budget
-            while queue and len(active) < self.max_active:
+            # admission: FIFO while the head fits the memory budget.  While
+            # solves are active, a head whose host-side set-up is unfinished
+            # waits (the GPU keeps stepping); admitted solves are built
+            # during the next round's steps and join after it.
+            admit = []
+            cells = sum(a["res"].n_fluid for a in active)
+            while queue and len(active) + len(admit) < self.max_active:
                 r = queue[0]
                 need = self.stepper.bytes_needed(r)
                 # memory held only while the solve is built
@@ -140,27 +145,38 @@ class Server:
                     continue
                 if used + need + extra > self.budget:
                     break
-                if (self.target_cells is not None and active and
-                        sum(a["res"].n_fluid for a in active) +
-                        self.stepper.cells_estimate(r) > self.target_cells):
+                if (self.target_cells is not None and (active or admit) and
+                        cells + self.stepper.cells_estimate(r) > self.target_cells):
+                    break
+                if (active or admit) and not self.stepper.ready(r):
                     break
                 queue.popleft()
-                handle = self.stepper.build(r)
-                res = results[r.rid]
-                res.admitted = self.clock() - t0
-                res.n_fluid = self.stepper.n_fluid(handle)
-                active.append({"req": r, "res": res, "handle": handle, "bytes": need,
-                               "jx": [], "refined": False})
+                results[r.rid].admitted = self.clock() - t0
+                admit.append((r, need))
                 used += need
-            if not active:
+                cells += self.stepper.cells_estimate(r)
+            if not active and not admit:
                 if pending:
                     wait = pending[0].arrival - (self.clock() - t0)
                     if wait > 0:
                         self.sleep(wait)
                 continue
-            # one round: K lockstep steps for every active solve
+
+            def start(r, need):
+                handle = self.stepper.build(r)
+                res = results[r.rid]
+                res.n_fluid = self.stepper.n_fluid(handle)
+                return {"req": r, "res": res, "handle": handle, "bytes": need, "jx": [],
+                        "refined": False}
+
+            if not active:   # nothing to overlap with: build, then step
+                active = [start(r, need) for r, need in admit]
+                admit = []
+            # one round: K lockstep steps for every active solve, with the
+            # builds of newly admitted solves overlapping them
             tb = self.clock()
             self.stepper.step([a["handle"] for a in active], self.K)
+            joined = [start(r, need) for r, need in admit]
             red = self.stepper.reduce([a["handle"] for a in active])
             busy += self.clock() - tb
             keep = []
@@ -199,7 +215,7 @@ class Server:
                         self.on_finish(res)
                 else:
                     keep.append(a)
-            active = keep
+            active = keep + joined
         makespan = self.clock() - t0
         done = [r for r in results.values() if not r.error]
         lat = [r.latency for r in done]
@@ -228,10 +244,15 @@ class MockStepper:
     request-specific limit geometrically, so the scheduler can be tested
     deterministically without a GPU."""
 
-    def __init__(self, rate_flups=1e9, bytes_per_cell=112, decay=0.9, fail_rid=None):
+    def __init__(self, rate_flups=1e9, bytes_per_cell=112, decay=0.9, fail_rid=None, prep_s=0.0):
         """refine() halves a solve's step rate (finer storage moves twice the
-        bytes) and can be called once per solve."""
+        bytes) and can be called once per solve.  prep_s: host set-up time
+        of a request (its geometry is ready prep_s after prepare()); a build
+        before that waits for it."""
         self.rate = rate_flups
+        self.prep_s = prep_s
+        self.prepared = {}
+        self.waited = 0.0
         self.bpc = bytes_per_cell
         self.decay = decay
         self.fail_rid = fail_rid
@@ -249,12 +270,21 @@ class MockStepper:
         return int(r.phi * r.L ** 3) * self.bpc
 
     def prepare(self, r):
-        pass
+        self.prepared.setdefault(r.rid, self.now)
+
+    def ready(self, r):
+        self.prepare(r)
+        return self.now >= self.prepared[r.rid] + self.prep_s
 
     def cells_estimate(self, r):
         return int(r.phi * r.L ** 3)
 
     def build(self, r):
+        self.prepare(r)
+        t_ready = self.prepared[r.rid] + self.prep_s
+        if self.now < t_ready:
+            self.waited += t_ready - self.now
+            self.now = t_ready
         h = {"req": r, "nf": int(r.phi * r.L ** 3), "t": 0}
         self.live[id(h)] = h
         self.built.append(r.rid)
@@ -314,6 +344,8 @@ class GpuStepper:
         import torch
         self.torch = torch
         self._ws = None
+        # builds run on a stream of their own so they overlap the steps
+        self._build_stream = torch.cuda.Stream()
         # Geometry generation runs on host threads while the GPU steps the
         # active solves (the blocking GPU calls release the interpreter lock).
         self._pool = concurrent.futures.ThreadPoolExecutor(max_workers=2)
@@ -330,6 +362,11 @@ class GpuStepper:
     def prepare(self, r):
         if r.rid not in self._labels:
             self._labels[r.rid] = self._pool.submit(self._geometry, r)
+
+    def ready(self, r):
+        """Whether the request's geometry has been generated."""
+        self.prepare(r)
+        return self._labels[r.rid].done()
 
     def _nf_bound(self, r):
         return int(math.ceil(r.phi * r.L ** 3 * 1.02)) + 64
@@ -364,16 +401,22 @@ class GpuStepper:
         return extra
 
     def build(self, r):
+        """Builds on the side stream (every torch copy and allocation of the
+        build is ordered there too) and returns once that stream is idle, so
+        the solve's buffers are complete when it joins the step stream."""
         from .inputs import PERIODIC_ALL
         self.prepare(r)
         lab = self._labels.pop(r.rid).result()
-        dom = self.lbm.SparseDomain(lab, PERIODIC_ALL, self.q, self.order, 64, stream=self.stream)
-        if self.index == "16":
-            dom.compact(stream=self.stream)
-        elif self.index == "runs":
-            dom.compact_runs(stream=self.stream, drop_index=True)
-        sol = self.lbm.Solver(dom, self.storage, self.dev_exp)
-        sol.init(stream=self.stream)
+        bs = self._build_stream
+        with self.torch.cuda.stream(bs):
+            dom = self.lbm.SparseDomain(lab, PERIODIC_ALL, self.q, self.order, 64, stream=bs)
+            if self.index == "16":
+                dom.compact(stream=bs)
+            elif self.index == "runs":
+                dom.compact_runs(stream=bs, drop_index=True)
+            sol = self.lbm.Solver(dom, self.storage, self.dev_exp)
+            sol.init(stream=bs)
+        bs.synchronize()
         coll = self.lbm.collision(self.lbm.COLL_TRT, tau=r.tau, magic=self.magic,
                                   force=(r.force, 0.0, 0.0))
         return {"req": r, "sol": sol, "coll": coll}

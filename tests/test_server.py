@@ -148,3 +148,37 @@ def test_refinement_falls_back_when_the_stepper_cannot_refine():
     res, met = server.Server(st, 1 << 40, K=100, tol=1e-6, max_steps=100_000, clock=st.clock,
                              sleep=st.sleep, refine_tol=1e-3).run(trace)
     assert all(r.converged and r.refined_at == 0 for r in res)
+
+
+def test_builds_overlap_steps_and_never_wait_while_solves_are_active():
+    """A request whose host-side set-up is unfinished is not admitted while
+    other solves run (they keep stepping); admitted solves are built during
+    the next round and join after it.  Ignoring readiness makes builds wait
+    with solves active and stretches the run."""
+
+    class Recording(server.MockStepper):
+        def __init__(self, gate, **kw):
+            super().__init__(**kw)
+            self.gate = gate
+            self.waits_while_busy = 0
+
+        def ready(self, r):
+            return super().ready(r) if self.gate else True
+
+        def build(self, r):
+            busy, before = bool(self.live), self.waited
+            h = super().build(r)
+            if self.waited > before and busy:
+                self.waits_while_busy += 1
+            return h
+
+    trace = server.make_trace(12, 40.0, seed=12, L_range=(32, 64))
+    out = {}
+    for gate in (True, False):
+        st = Recording(gate, rate_flups=2e8, prep_s=0.2)
+        res, met = server.Server(st, 1 << 40, K=100, clock=st.clock, sleep=st.sleep).run(trace)
+        assert met["completed"] == 12 and all(r.converged for r in res)
+        assert st.built == sorted(st.built)
+        out[gate] = (st.waits_while_busy, met["makespan_s"])
+    assert out[True][0] == 0 and out[False][0] > 0
+    assert out[True][1] < out[False][1]
