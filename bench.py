@@ -94,9 +94,10 @@ def cpu_baseline(lab, per, q, tau, magic, force, n_fluid, budget_s):
 
 
 def recorded_traffic(workload_key):
-    """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 counter summaries in profiles/, if one matches this workload
-    and was taken on the current kernel sources; else None."""
+    """HBM bytes per launch of the dominant (odd-step) kernel and of the
+    even-step kernel from the committed rocprofv3 counter summaries in
+    profiles/, if one matches this workload and was taken on the current
+    kernel sources; else None."""
     import glob
 
     from paper_2408_06880_amd import kernel_source_hash
@@ -108,8 +109,10 @@ def recorded_traffic(workload_key):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
         if kv.get("traffic_workload") == workload_key and kv.get("traffic_source_hash") == h:
-            return float(kv["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
-    return None, None
+            even = kv.get("traffic_even_bytes_per_launch")
+            return (float(kv["traffic_bytes_per_launch"]), float(even) if even else None,
+                    os.path.relpath(path, ROOT))
+    return None, None, None
 
 
 def _device_used(torch):
@@ -577,7 +580,7 @@ def main():
         workload = (f"sparse D3Q27 cumulant AA (tau 0.8), {args.L}^3 vessel tree "
                     f"(root r 24, ratio 0.79, seed {info['seed']}, {info['n_outlets']} outlets, "
                     f"phi={info['phi']:.4f}), UBB inlet u_z={info['inlet_u']}, pressure outlets")
-    traffic, traffic_src = recorded_traffic(
+    traffic, traffic_even, traffic_src = recorded_traffic(
         f"{workload}; storage={args.storage}; order={args.order}; index={index_form}"
         + ("; scheme=pull" if args.scheme == "pull" else ""))
     out = {
@@ -605,6 +608,9 @@ def main():
                    "stride": dom.stride},
         "pct_hbm_peak": round(100.0 * mflups * 1e6 * b_alg_m / (HBM_PEAK_GBS * 1e9), 2),
         "bytes_per_flup_alg": b_alg_m,
+        # HBM bytes per update from the counter summary (odd + even launch)
+        "bytes_per_flup_measured": (round((traffic + traffic_even) / (2 * nf), 2)
+                                    if traffic and traffic_even and args.scheme == "aa" else None),
         "pct_hbm_peak_index_form": round(100.0 * mflups * 1e6 * b_alg / (HBM_PEAK_GBS * 1e9), 2),
         "bytes_per_flup_index_form": b_alg,
         "roofline": {"bound": "hbm",
