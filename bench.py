@@ -54,10 +54,21 @@ def copy_bandwidth(lbm, torch, nbytes=2 << 30, reps=10):
     return 2 * nbytes / s / 1e9
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(lab, per, q, tau, magic, force, n_fluid, budget_s):
     """The FP64 oracle (dense two-array pull, OpenMP over z-planes) on the
     same geometry: one untimed step (first touch of the second array), then
-    whole-grid steps until `budget_s` seconds have passed."""
+    whole-grid steps until `budget_s` seconds have passed on all threads,
+    then the same on one thread for a third of the budget."""
     import ctypes
 
     import numpy as np
@@ -78,19 +89,33 @@ def cpu_baseline(lab, per, q, tau, magic, force, n_fluid, budget_s):
 
     step(A, B)
     A, B = B, A
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        step(A, B)
-        A, B = B, A
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s:
-            break
+
+    def timed(budget):
+        nonlocal A, B
+        steps = 0
+        t0 = time.perf_counter()
+        while True:
+            step(A, B)
+            A, B = B, A
+            steps += 1
+            el = time.perf_counter() - t0
+            if el >= budget:
+                return steps, el
+
+    threads = oracle.num_threads()
+    steps, el = timed(budget_s)
+    oracle.set_num_threads(1)
+    try:
+        steps1, el1 = timed(budget_s / 3)
+    finally:
+        oracle.set_num_threads(threads)
     return {"value": round(n_fluid * steps / el / 1e6, 3), "unit": "MFLUPS",
-            "cores": oracle.num_threads(), "kind": "oracle",
+            "cores": threads, "kind": "oracle",
             "sample": f"{steps} dense FP64 pull TRT step(s) of the full {nx}x{ny}x{nz} geometry "
-                      f"({n_fluid} fluid cells) after one untimed step, {el:.1f} s"}
+                      f"({n_fluid} fluid cells) after one untimed step, {el:.1f} s",
+            "single_thread_value": round(n_fluid * steps1 / el1 / 1e6, 3),
+            "single_thread_sample": f"{steps1} step(s), {el1:.1f} s",
+            "host_cpus": os.cpu_count(), "cpu_model": _cpu_model()}
 
 
 def recorded_traffic(workload_key):

@@ -105,6 +105,7 @@ def _load():
         vp = ctypes.c_void_p
         i32, i64, u32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
         lib.orc_num_threads.restype = ctypes.c_int
+        lib.orc_set_num_threads.argtypes = [ctypes.c_int]
         lib.orc_stencil_tables.argtypes = [i32, vp, vp, vp]
         lib.orc_collide_cells.argtypes = [P, i64, vp, vp]
         lib.orc_mrt_matrix.argtypes = [vp]
@@ -137,6 +138,11 @@ def _check(rc, what):
 def num_threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Thread count of the oracle's later parallel loops (for timings)."""
+    _load().orc_set_num_threads(int(n))
 
 
 def stencil(q):

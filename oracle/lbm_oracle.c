@@ -98,6 +98,9 @@ int orc_stencil_tables(int q, int32_t* c_out /* [q*3] */, double* w_out /* [q] *
 /* Threads the OpenMP loops use (reported with CPU timings). */
 int orc_num_threads(void) { return omp_get_max_threads(); }
 
+/* Sets the thread count of later parallel loops (CPU timings only). */
+void orc_set_num_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+
 /* ------------------------------------------------------------------ */
 /* Parameters.                                                          */
 /* ------------------------------------------------------------------ */
