@@ -200,6 +200,8 @@ def memory_study(L=256, phis=(0.2, 0.4, 0.6, 0.8, 0.95), storages=("f64", "f32",
                 row[form] = {"measured_bytes": used, "exact_bytes": exact,
                              "build_peak_bytes": peak,
                              "measured_per_fluid_cell": round(used / nf, 2)}
+                if form == "runs":
+                    row[form]["index_bytes_per_fluid_cell"] = round(dom.runs_bytes / nf, 3)
                 del obj, fields
                 if form != "dense":
                     del dom
@@ -480,7 +482,8 @@ def main():
     elif args.index == "run":
         if args.scheme == "pull":
             raise SystemExit("--scheme pull reads the int32 or 16-bit index-list, not runs")
-        runs_bpc = dom.compact_runs()
+        # AA steps, moments and reductions need only the run form
+        runs_bpc = dom.compact_runs(drop_index=True)
         index_form = "runs"
         log(f"run-compressed index-list: {runs_bpc:.2f} bytes per fluid cell")
     torch.cuda.synchronize()
@@ -493,6 +496,7 @@ def main():
         b, x = lbm.lbm_get_launch(lbm.KERNEL_EVEN, q, storage)
         lbm.lbm_set_launch(lbm.KERNEL_EVEN, q, storage, b, x, 0, args.even_cells)
     sol = lbm.Solver(dom, storage, dev_exp)
+    solve_bytes = dom.device_bytes() + sol.device_bytes()
     if vessel:
         coll = lbm.collision(lbm.COLL_CUMULANT, tau=0.8, omega_bulk=1.0, force=force)
     else:
@@ -655,6 +659,9 @@ def main():
         "copy_kernel_gbs": round(copy_gbs, 1) if copy_gbs else None,
         "pct_copy_bw": round(100.0 * mflups * 1e6 * b_alg_m / (copy_gbs * 1e9), 2) if copy_gbs else None,
         "builder_ms": round(build_ms, 2),
+        # device buffers of the solve: lists, PDF-list, reduction workspace
+        "solve_device_bytes": solve_bytes,
+        "solve_bytes_per_fluid_cell": round(solve_bytes / nf, 2),
         "dense_comparator": dense,
         "serving": serving,
         "cpu_baseline": cpu,
