@@ -118,11 +118,12 @@ def cpu_baseline(lab, per, q, tau, magic, force, n_fluid, budget_s):
             "host_cpus": os.cpu_count(), "cpu_model": _cpu_model()}
 
 
-def recorded_traffic(workload_key):
+def recorded_traffic(workload_key, launch_odd):
     """HBM bytes per launch of the dominant (odd-step) kernel and of the
     even-step kernel from the committed rocprofv3 counter summaries in
     profiles/, if one matches this workload and was taken on the current
-    kernel sources; else None."""
+    kernel sources with the odd kernel's current launch configuration;
+    else None."""
     import glob
 
     from paper_2408_06880_amd import kernel_source_hash
@@ -133,7 +134,8 @@ def recorded_traffic(workload_key):
             if line.startswith("traffic_") and ":" in line:
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-        if kv.get("traffic_workload") == workload_key and kv.get("traffic_source_hash") == h:
+        if (kv.get("traffic_workload") == workload_key and kv.get("traffic_source_hash") == h
+                and kv.get("traffic_launch") == "/".join(map(str, launch_odd))):
             even = kv.get("traffic_even_bytes_per_launch")
             return (float(kv["traffic_bytes_per_launch"]), float(even) if even else None,
                     os.path.relpath(path, ROOT))
@@ -376,6 +378,11 @@ def main():
     ap.add_argument("--even-cells", type=int, default=0, choices=[0, 1, 2],
                     help="cells per thread of the even-step kernel (0: the library's "
                          "default, two for 16-bit storage)")
+    ap.add_argument("--odd-groups", type=int, default=None,
+                    help="resident workgroups per CU of the odd-step kernel (0: uncapped; "
+                         "default: the library's table)")
+    ap.add_argument("--even-groups", type=int, default=None,
+                    help="the same for the even-step kernel")
     ap.add_argument("--scheme", default="aa", choices=["aa", "pull"],
                     help="aa: in-place AA steps; pull: two-array pull steps (comparison)")
     ap.add_argument("--requests", type=int, default=48,
@@ -493,8 +500,14 @@ def main():
         b, x = lbm.lbm_get_launch(lbm.KERNEL_ODD, q, storage)
         lbm.lbm_set_launch(lbm.KERNEL_ODD, q, storage, 256, x, 1)
     if args.even_cells:
-        b, x = lbm.lbm_get_launch(lbm.KERNEL_EVEN, q, storage)
-        lbm.lbm_set_launch(lbm.KERNEL_EVEN, q, storage, b, x, 0, args.even_cells)
+        cfg = list(lbm.lbm_get_launch(lbm.KERNEL_EVEN, q, storage, full=True))
+        cfg[3] = args.even_cells
+        lbm.lbm_set_launch(lbm.KERNEL_EVEN, q, storage, *cfg)
+    for kern, g in ((lbm.KERNEL_ODD, args.odd_groups), (lbm.KERNEL_EVEN, args.even_groups)):
+        if g is not None:
+            cfg = list(lbm.lbm_get_launch(kern, q, storage, full=True))
+            cfg[4] = g
+            lbm.lbm_set_launch(kern, q, storage, *cfg)
     sol = lbm.Solver(dom, storage, dev_exp)
     solve_bytes = dom.device_bytes() + sol.device_bytes()
     if vessel:
@@ -611,7 +624,8 @@ def main():
                     f"phi={info['phi']:.4f}), UBB inlet u_z={info['inlet_u']}, pressure outlets")
     traffic, traffic_even, traffic_src = recorded_traffic(
         f"{workload}; storage={args.storage}; order={args.order}; index={index_form}"
-        + ("; scheme=pull" if args.scheme == "pull" else ""))
+        + ("; scheme=pull" if args.scheme == "pull" else ""),
+        lbm.lbm_get_launch(lbm.KERNEL_ODD, q, storage, full=True))
     out = {
         "metric": METRIC if not vessel else
         "MFLUPS + % HBM BW, sparse D3Q27 cumulant 512^3 vessel tree",
@@ -633,6 +647,8 @@ def main():
                    "scheme": args.scheme, "pipelined_odd": args.pipelined,
                    "even_cells_per_thread": lbm.lbm_get_launch(lbm.KERNEL_EVEN, q, storage,
                                                                full=True)[3],
+                   "launch_odd": lbm.lbm_get_launch(lbm.KERNEL_ODD, q, storage, full=True),
+                   "launch_even": lbm.lbm_get_launch(lbm.KERNEL_EVEN, q, storage, full=True),
                    "index_escaped_fraction": escaped,
                    "stride": dom.stride},
         "pct_hbm_peak": round(100.0 * mflups * 1e6 * b_alg_m / (HBM_PEAK_GBS * 1e9), 2),

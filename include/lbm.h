@@ -377,6 +377,11 @@ typedef struct {
                       /* state of the launch has an even stride (one cell      */
                       /* otherwise); 0 or 1 = one cell (the only choice for    */
                       /* the other kernels)                                    */
+  int32_t max_groups_per_cu; /* odd and even AA kernels: 0 = as many resident */
+                      /* workgroups per CU as registers allow; n in [2, 16] =  */
+                      /* at most n (dynamic LDS is reserved for the purpose;   */
+                      /* the kernels use none).  Not for pipelined or dense    */
+                      /* launches; pull steps run uncapped.                    */
 } lbm_launch;
 
 /* Set / get the launch configuration used for (kernel, q, storage) from

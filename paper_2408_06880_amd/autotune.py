@@ -2,8 +2,8 @@
 
 For each kernel kind (odd step, even step, dense comparator) of a given
 (stencil, storage) pair, time every candidate (workgroup size x XCD-aware tile
-order, and for the even step one or two cells per thread) on a representative
-solve and keep the fastest.  Results go to a JSON cache keyed by device,
+order x cap on resident workgroups per CU, and for the even step one or two
+cells per thread) on a representative solve and keep the fastest.  Results go to a JSON cache keyed by device,
 kernel, stencil, storage and a fluid-cell size bucket; `apply()` loads a cache
 and installs the entries through `lbm_set_launch`.  The arithmetic does not
 depend on the launch configuration (every candidate performs each cell's
@@ -18,6 +18,7 @@ import os
 BLOCKS = (64, 128, 256)
 XCD = (0, 1)
 CELLS = (1, 2)          # cells per thread, even-step kernel only
+GROUPS = (0, 2, 3, 4)   # resident workgroups per CU (0: as registers allow)
 KERNEL_NAMES = {0: "odd", 1: "even", 2: "dense"}
 
 
@@ -31,29 +32,31 @@ def cache_key(device: str, kernel: int, q: int, storage: int, bucket: int) -> st
 
 
 def choose(timings: dict) -> tuple:
-    """timings: {(block, xcd[, cells]): seconds} -> the fastest configuration;
-    ties keep the larger block (fewer workgroups), then XCD order on, then
-    fewer cells per thread."""
+    """timings: {(block, xcd[, cells[, groups]]): seconds} -> the fastest
+    configuration; ties keep the larger block (fewer workgroups), then XCD
+    order on, then fewer cells per thread, then no residency cap."""
     best = None
     for cfg, t in timings.items():
-        key = (t, -cfg[0], -cfg[1], *cfg[2:])
+        key = (t, -cfg[0], -cfg[1], *cfg[2:3], *(g if g else -1 for g in cfg[3:]))
         if best is None or key < best[0]:
             best = (key, cfg)
     return best[1]
 
 
-def candidates(kernel, blocks=BLOCKS, xcds=XCD, cells=CELLS):
-    """(block, xcd, cells per thread) candidates of one kernel kind."""
+def candidates(kernel, blocks=BLOCKS, xcds=XCD, cells=CELLS, groups=GROUPS):
+    """(block, xcd, cells per thread, groups per CU) candidates of one kernel
+    kind."""
     cs = cells if kernel == 1 else (1,)
-    return [(b, x, c) for b in blocks for x in xcds for c in cs]
+    return [(b, x, c, g) for b in blocks for x in xcds for c in cs for g in groups]
 
 
-def tune(measure, kernels=(0, 1), blocks=BLOCKS, xcds=XCD, cells=CELLS):
-    """measure(kernel, block, xcd, cells) -> seconds per launch.  Returns
-    {kernel: ((block, xcd, cells), {cfg: seconds})}."""
+def tune(measure, kernels=(0, 1), blocks=BLOCKS, xcds=XCD, cells=CELLS, groups=GROUPS):
+    """measure(kernel, block, xcd, cells, groups) -> seconds per launch.
+    Returns {kernel: ((block, xcd, cells, groups), {cfg: seconds})}."""
     out = {}
     for k in kernels:
-        timings = {cfg: float(measure(k, *cfg)) for cfg in candidates(k, blocks, xcds, cells)}
+        timings = {cfg: float(measure(k, *cfg))
+                   for cfg in candidates(k, blocks, xcds, cells, groups)}
         out[k] = (choose(timings), timings)
     return out
 
@@ -65,9 +68,9 @@ def gpu_measure(solver, coll, steps=8):
 
     from . import lbm
 
-    def measure(kernel, block, xcd, cells=1):
+    def measure(kernel, block, xcd, cells=1, groups=0):
         q, st = solver.domain.q, solver.storage
-        lbm.lbm_set_launch(kernel, q, st, block, xcd, 0, cells)
+        lbm.lbm_set_launch(kernel, q, st, block, xcd, 0, cells, groups)
         solver.step(2, coll)
         torch.cuda.synchronize()
         evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps + 1)]
@@ -99,10 +102,10 @@ def tune_solver(solver, coll, cache_path=None, steps=8):
     dev = device_name()
     q, st, nf = solver.domain.q, solver.storage, solver.domain.n_fluid
     entries = {}
-    for k, ((b, x, c), timings) in res.items():
-        lbm.lbm_set_launch(k, q, st, b, x, 0, c)
+    for k, ((b, x, c, g), timings) in res.items():
+        lbm.lbm_set_launch(k, q, st, b, x, 0, c, g)
         entries[cache_key(dev, k, q, st, size_bucket(nf))] = {
-            "block": b, "xcd_remap": x, "cells_per_thread": c,
+            "block": b, "xcd_remap": x, "cells_per_thread": c, "max_groups_per_cu": g,
             "timings_us": {"/".join(map(str, cfg)): round(t * 1e6, 2)
                            for cfg, t in timings.items()}}
     if cache_path:
@@ -154,6 +157,6 @@ def apply(cache_path, q, storage, n_fluid, device=None):
         e = lookup(cache, device, k, q, storage, n_fluid)
         if e is not None:
             lbm.lbm_set_launch(k, q, storage, e["block"], e["xcd_remap"], 0,
-                               e.get("cells_per_thread", 1))
+                               e.get("cells_per_thread", 1), e.get("max_groups_per_cu", 0))
             n += 1
     return n

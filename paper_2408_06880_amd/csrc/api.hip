@@ -39,6 +39,7 @@ lbm_status hip_fail(hipError_t e, const char* where) {
   } while (0)
 
 // ------------------------------------------------------- launch table
+constexpr uint32_t kLdsPerCu = 160u * 1024u;  // LDS bytes per CU (gfx950)
 std::mutex g_launch_mu;
 lbm_launch g_launch[3][2][5];  // kernel x (q19, q27) x storage
 bool g_launch_init = false;
@@ -50,17 +51,33 @@ void launch_defaults() {
   // Measured on MI355X: the gather/scatter (odd) kernel gains from keeping
   // neighbouring tiles on one XCD; the streaming kernels do not.  The even
   // kernel takes two cells per thread for 16-bit storage (2-byte lanes),
-  // one otherwise.
+  // one otherwise.  Fewer resident workgroups than registers allow stream
+  // better for D3Q19 on the 256^3 packing (block 256): FP32 and FP32-dev
+  // odd step at 4 per CU (FP32 360 -> 355 us), even step at 3 (FP32-dev
+  // 262 -> 253 us), FP64 even at 2 (565 -> 539 us); 16-bit storage, the
+  // FP64 odd step and the D3Q27 kernels run fastest uncapped.
   for (int k = 0; k < 3; ++k)
-    for (auto& b : g_launch[k])
+    for (int qi = 0; qi < 2; ++qi)
       for (int st = 0; st < 5; ++st) {
-        lbm_launch& c = b[st];
+        lbm_launch& c = g_launch[k][qi][st];
         c.block = 256;
         c.xcd_remap = (k == LBM_KERNEL_ODD) ? 1 : 0;
         c.pipelined = 0;
         c.cells_per_thread = (k == LBM_KERNEL_EVEN && is16(st)) ? 2 : 1;
+        c.max_groups_per_cu = 0;
+        if (qi == 0 && (st == LBM_STORE_F32 || st == LBM_STORE_F32DEV))
+          c.max_groups_per_cu = k == LBM_KERNEL_ODD ? 4 : (k == LBM_KERNEL_EVEN ? 3 : 0);
+        if (qi == 0 && st == LBM_STORE_F64 && k == LBM_KERNEL_EVEN) c.max_groups_per_cu = 2;
       }
   g_launch_init = true;
+}
+
+// Dynamic LDS per workgroup that lets at most n workgroups share a CU's
+// 160 KB (the step kernels use no LDS): just over 160 KB / (n + 1), in
+// 512-byte units; 0 for no cap.
+uint32_t cap_lds_bytes(int n) {
+  if (n <= 0) return 0;
+  return (kLdsPerCu / (uint32_t)(n + 1) / 512u + 1u) * 512u;
 }
 
 lbm_launch get_cfg(int kernel, int q, int storage) {
@@ -262,9 +279,10 @@ lbm_status link_update(const lbm_state* s, const lbm_bspec* bs, hipStream_t st) 
 }
 
 hipError_t launch_aa(int q, int coll, int storage, int mode, int idx, const StepArgs& a,
-                     int block, hipStream_t st) {
-  if (q == 19) return launch_aa_q19(coll, storage, mode, idx, a, block, st);
-  return launch_aa_q27(coll, storage, mode, idx, a, block, st);
+                     const lbm_launch& cfg, hipStream_t st) {
+  const uint32_t lds = cap_lds_bytes(cfg.max_groups_per_cu);
+  if (q == 19) return launch_aa_q19(coll, storage, mode, idx, a, cfg.block, lds, st);
+  return launch_aa_q27(coll, storage, mode, idx, a, cfg.block, lds, st);
 }
 
 uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
@@ -273,7 +291,7 @@ uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); 
 
 extern "C" {
 
-int32_t lbm_abi_version(void) { return 3; }
+int32_t lbm_abi_version(void) { return 4; }
 
 const char* lbm_last_error(void) { return g_err.c_str(); }
 
@@ -288,6 +306,12 @@ lbm_status lbm_set_launch(int32_t kernel, int32_t q, int32_t storage, const lbm_
       (cfg->cells_per_thread == 2 && kernel != LBM_KERNEL_EVEN))
     return fail(LBM_EINVAL, "cells_per_thread must be 0, 1, or 2 for the even kernel (got %d)",
                 cfg->cells_per_thread);
+  if (cfg->max_groups_per_cu != 0 &&
+      (cfg->max_groups_per_cu < 2 || cfg->max_groups_per_cu > 16 ||
+       kernel == LBM_KERNEL_DENSE || cfg->pipelined))
+    return fail(LBM_EINVAL,
+                "max_groups_per_cu must be 0, or 2..16 for the sparse step kernels (got %d)",
+                cfg->max_groups_per_cu);
   std::lock_guard<std::mutex> lk(g_launch_mu);
   launch_defaults();
   g_launch[kernel][q == 27 ? 1 : 0][storage] = *cfg;
@@ -532,7 +556,7 @@ static lbm_status step_group(lbm_state* const* states, const lbm_collision* cons
         a.nseg = ns;
         a.ntiles = tiles;
         const int mode = !odd ? (cpt == 2 ? 4 : 0) : (form == IDX_16 && cfg.pipelined == 1 ? 3 : 1);
-        if (ns > 0) HIP_TRY(launch_aa(q, kind, storage, mode, form, a, cfg.block, st), "AA step");
+        if (ns > 0) HIP_TRY(launch_aa(q, kind, storage, mode, form, a, cfg, st), "AA step");
       }
       if (!odd) break;
     }
@@ -565,7 +589,10 @@ lbm_status lbm_step_pull(lbm_state* s, void** spare, int32_t n_steps, const lbm_
   if (n_steps < 0 || (n_steps & 1)) return fail(LBM_EINVAL, "n_steps must be even and >= 0");
   if (s->t & 1) return fail(LBM_ESTATE, "pull steps need the natural slot layout (even t)");
   hipStream_t st = (hipStream_t)stream;
-  const lbm_launch cfg = get_cfg(LBM_KERNEL_ODD, s->layout.q, s->storage);
+  // the odd kernel's workgroup size and tile order; no residency cap (the
+  // caps were measured for the AA kernels)
+  lbm_launch cfg = get_cfg(LBM_KERNEL_ODD, s->layout.q, s->storage);
+  cfg.max_groups_per_cu = 0;
   // the pull kernel reads the compact or the int32 index-list
   if (s->layout.n_fluid > 0 && !s->index)
     return fail(LBM_EINVAL, "pull steps need the int32 index-list");
@@ -583,7 +610,7 @@ lbm_status lbm_step_pull(lbm_state* s, void** spare, int32_t n_steps, const lbm_
       a.seg[0] = g;
       a.nseg = 1;
       a.ntiles = ceil_div(g.nf, (uint64_t)cfg.block);
-      HIP_TRY(launch_aa(s->layout.q, c->kind, s->storage, 2, idx, a, cfg.block, st),
+      HIP_TRY(launch_aa(s->layout.q, c->kind, s->storage, 2, idx, a, cfg, st),
               "pull step");
       void* tmp = s->pdf;
       s->pdf = *spare;

@@ -10,10 +10,11 @@
 namespace lbm {
 
 // AA step kernels (step_q19.hip, step_q27.hip); mode 0 even, 1 odd, 2 pull
+// (lds: dynamic LDS bytes reserved per workgroup, to cap residency)
 hipError_t launch_aa_q19(int coll, int storage, int mode, int idx, const StepArgs& a,
-                         int block, hipStream_t st);
+                         int block, uint32_t lds, hipStream_t st);
 hipError_t launch_aa_q27(int coll, int storage, int mode, int idx, const StepArgs& a,
-                         int block, hipStream_t st);
+                         int block, uint32_t lds, hipStream_t st);
 
 // Boundary-class coefficients of one solve, precomputed on the host:
 // for class c, type[c] in {0 noslip, 1 UBB, 2 pressure}; u[c][3]; rho[c].

@@ -25,6 +25,8 @@
 #include "cumulant.hpp"
 #include "mrt.hpp"
 
+#include <atomic>
+
 namespace lbm {
 
 template <int Q, int COLL, class R>
@@ -327,56 +329,60 @@ __global__ __launch_bounds__(256) void k_odd_pipe(const StepArgs a) {
   }
 }
 
-// Host-side dispatch over (collision, storage, parity) for one Q.
+// Host-side dispatch over (collision, storage, parity) for one Q.  `lds`:
+// dynamic LDS reserved per workgroup (the step kernels use none); it caps
+// how many workgroups share a CU.
 template <int Q, int COLL, int ST>
-inline hipError_t launch_aa_cs(int mode, int idx, const StepArgs& a, int block,
+inline hipError_t launch_aa_cs(int mode, int idx, const StepArgs& a, int block, uint32_t lds,
                                hipStream_t st) {
   dim3 grid(a.ntiles), blk(block);
   if (mode == MODE_ODD_PIPE) {
     // resident workgroups of this kernel, rounded down to a multiple of 8
-    static int resident = 0;
-    if (resident == 0) {
+    // (computed once per kernel instance: every device is the same gfx950)
+    static std::atomic<int> resident{0};
+    if (resident.load() == 0) {
       int per_cu = 0, dev = 0, cus = 0;
-      hipGetDevice(&dev);
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_odd_pipe<Q, COLL, ST>, 256, 0);
-      resident = per_cu * cus;
-      if (resident < 8) resident = 8;
+      hipError_t e = hipGetDevice(&dev);
+      if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_odd_pipe<Q, COLL, ST>, 256, 0);
+      if (e != hipSuccess) return e;
+      resident.store(per_cu * cus < 8 ? 8 : per_cu * cus);
     }
-    const int per = resident * 256 / block;
+    const int per = resident.load() * 256 / block;
     uint32_t g = a.ntiles < (uint32_t)per ? a.ntiles : (uint32_t)per;
     if (g >= 8) g &= ~7u;
-    hipLaunchKernelGGL((k_odd_pipe<Q, COLL, ST>), dim3(g), blk, 0, st, a);
+    hipLaunchKernelGGL((k_odd_pipe<Q, COLL, ST>), dim3(g), blk, lds, st, a);
     return hipGetLastError();
   }
   if (mode == MODE_EVEN2) {
-    hipLaunchKernelGGL((k_even_pair<Q, COLL, ST>), grid, blk, 0, st, a);
+    hipLaunchKernelGGL((k_even_pair<Q, COLL, ST>), grid, blk, lds, st, a);
     return hipGetLastError();
   }
   if (mode == MODE_ODD && idx == IDX_RUN)
-    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_ODD, IDX_RUN>), grid, blk, 0, st, a);
+    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_ODD, IDX_RUN>), grid, blk, lds, st, a);
   else if (mode == MODE_ODD && idx == IDX_16)
-    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_ODD, IDX_16>), grid, blk, 0, st, a);
+    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_ODD, IDX_16>), grid, blk, lds, st, a);
   else if (mode == MODE_ODD)
-    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_ODD, IDX_I32>), grid, blk, 0, st, a);
+    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_ODD, IDX_I32>), grid, blk, lds, st, a);
   else if (mode == MODE_PULL && idx == IDX_16)
-    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_PULL, IDX_16>), grid, blk, 0, st, a);
+    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_PULL, IDX_16>), grid, blk, lds, st, a);
   else if (mode == MODE_PULL)
-    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_PULL, IDX_I32>), grid, blk, 0, st, a);
+    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_PULL, IDX_I32>), grid, blk, lds, st, a);
   else
-    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_EVEN, IDX_I32>), grid, blk, 0, st, a);
+    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_EVEN, IDX_I32>), grid, blk, lds, st, a);
   return hipGetLastError();
 }
 
 template <int Q, int COLL>
 inline hipError_t launch_aa_c(int storage, int mode, int idx, const StepArgs& a, int block,
-                              hipStream_t st) {
+                              uint32_t lds, hipStream_t st) {
   switch (storage) {
-    case ST_F64: return launch_aa_cs<Q, COLL, ST_F64>(mode, idx, a, block, st);
-    case ST_F32: return launch_aa_cs<Q, COLL, ST_F32>(mode, idx, a, block, st);
-    case ST_F16DEV: return launch_aa_cs<Q, COLL, ST_F16DEV>(mode, idx, a, block, st);
-    case ST_BF16DEV: return launch_aa_cs<Q, COLL, ST_BF16DEV>(mode, idx, a, block, st);
-    case ST_F32DEV: return launch_aa_cs<Q, COLL, ST_F32DEV>(mode, idx, a, block, st);
+    case ST_F64: return launch_aa_cs<Q, COLL, ST_F64>(mode, idx, a, block, lds, st);
+    case ST_F32: return launch_aa_cs<Q, COLL, ST_F32>(mode, idx, a, block, lds, st);
+    case ST_F16DEV: return launch_aa_cs<Q, COLL, ST_F16DEV>(mode, idx, a, block, lds, st);
+    case ST_BF16DEV: return launch_aa_cs<Q, COLL, ST_BF16DEV>(mode, idx, a, block, lds, st);
+    case ST_F32DEV: return launch_aa_cs<Q, COLL, ST_F32DEV>(mode, idx, a, block, lds, st);
   }
   return hipErrorInvalidValue;
 }

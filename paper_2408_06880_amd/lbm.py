@@ -81,7 +81,7 @@ class lbm_dense_state(ctypes.Structure):
 
 class lbm_launch(ctypes.Structure):
     _fields_ = [("block", _i32), ("xcd_remap", _i32), ("pipelined", _i32),
-                ("cells_per_thread", _i32)]
+                ("cells_per_thread", _i32), ("max_groups_per_cu", _i32)]
 
 
 class LbmError(RuntimeError):
@@ -312,18 +312,21 @@ def lbm_dense_step(state, n_steps, coll, stream=None):
           _stream(stream))
 
 
-def lbm_set_launch(kernel, q, storage, block=256, xcd_remap=1, pipelined=0, cells_per_thread=1):
-    cfg = lbm_launch(block, xcd_remap, pipelined, cells_per_thread)
+def lbm_set_launch(kernel, q, storage, block=256, xcd_remap=1, pipelined=0, cells_per_thread=1,
+                   max_groups_per_cu=0):
+    cfg = lbm_launch(block, xcd_remap, pipelined, cells_per_thread, max_groups_per_cu)
     _call("lbm_set_launch", kernel, q, storage, ctypes.byref(cfg))
 
 
 def lbm_get_launch(kernel, q, storage, full=False):
     """(block, xcd_remap), or with full=True (block, xcd_remap, pipelined,
-    cells_per_thread)."""
+    cells_per_thread, max_groups_per_cu): the argument order of
+    lbm_set_launch."""
     cfg = lbm_launch()
     _call("lbm_get_launch", kernel, q, storage, ctypes.byref(cfg))
     if full:
-        return (cfg.block, cfg.xcd_remap, cfg.pipelined, cfg.cells_per_thread)
+        return (cfg.block, cfg.xcd_remap, cfg.pipelined, cfg.cells_per_thread,
+                cfg.max_groups_per_cu)
     return (cfg.block, cfg.xcd_remap)
 
 

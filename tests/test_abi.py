@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     lib = lbm.load()
     for name in declared_functions():
         assert hasattr(lib, name), name
-    assert lbm.lbm_abi_version() == 3
+    assert lbm.lbm_abi_version() == 4
 
 
 def test_struct_sizes_match_header_layout():
@@ -37,6 +37,7 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(lbm.lbm_bspec) == 8 + 8 * 40
     assert ctypes.sizeof(lbm.lbm_reduction) == 48
     assert ctypes.sizeof(lbm.lbm_dense_state) == 32 + 16 + 8
+    assert ctypes.sizeof(lbm.lbm_launch) == 5 * 4
 
 
 def test_workspace_queries():
@@ -135,9 +136,16 @@ def test_batch_mismatch_rejected_on_host():
 
 def test_launch_table_roundtrip():
     old = lbm.lbm_get_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F16DEV, full=True)
-    assert old == (256, 0, 0, 2)          # 16-bit storage: two cells per thread
-    assert lbm.lbm_get_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F32, full=True) == (256, 0, 0, 1)
-    assert lbm.lbm_get_launch(lbm.KERNEL_ODD, 19, lbm.STORE_F32, full=True) == (256, 1, 0, 1)
+    assert old == (256, 0, 0, 2, 0)       # 16-bit storage: two cells per thread
+    assert lbm.lbm_get_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F32, full=True) == (256, 0, 0, 1, 0)
+    # measured residency caps: D3Q19 FP32 and FP32-dev odd 4 and even 3, FP64 even 2
+    assert lbm.lbm_get_launch(lbm.KERNEL_ODD, 19, lbm.STORE_F32, full=True) == (256, 1, 0, 1, 4)
+    assert lbm.lbm_get_launch(lbm.KERNEL_EVEN, 19, lbm.STORE_F32, full=True) == (256, 0, 0, 1, 3)
+    assert lbm.lbm_get_launch(lbm.KERNEL_EVEN, 19, lbm.STORE_F64, full=True) == (256, 0, 0, 1, 2)
+    assert lbm.lbm_get_launch(lbm.KERNEL_ODD, 19, lbm.STORE_F64, full=True) == (256, 1, 0, 1, 0)
+    assert lbm.lbm_get_launch(lbm.KERNEL_EVEN, 19, lbm.STORE_F32DEV, full=True) == (256, 0, 0, 1, 3)
+    assert lbm.lbm_get_launch(lbm.KERNEL_ODD, 27, lbm.STORE_F32, full=True) == (256, 1, 0, 1, 0)
+    assert lbm.lbm_get_launch(lbm.KERNEL_DENSE, 19, lbm.STORE_F32, full=True)[4] == 0
     lbm.lbm_set_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F16DEV, 128, 0)
     assert lbm.lbm_get_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F16DEV) == (128, 0)
     lbm.lbm_set_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F16DEV, *old)
@@ -145,6 +153,14 @@ def test_launch_table_roundtrip():
     # two cells per thread exist for the even kernel only
     expect(lbm.LBM_EINVAL, lbm.lbm_set_launch, lbm.KERNEL_ODD, 19, lbm.STORE_F32, 256, 1, 0, 2)
     expect(lbm.LBM_EINVAL, lbm.lbm_set_launch, lbm.KERNEL_EVEN, 19, lbm.STORE_F32, 256, 0, 0, 3)
+    # residency caps: 0 or 2..16, AA kernels only, not with the pipelined odd kernel
+    for bad in (1, 17, -1):
+        expect(lbm.LBM_EINVAL, lbm.lbm_set_launch, lbm.KERNEL_ODD, 19, lbm.STORE_F32, 256, 1, 0,
+               1, bad)
+    expect(lbm.LBM_EINVAL, lbm.lbm_set_launch, lbm.KERNEL_DENSE, 19, lbm.STORE_F32, 256, 0, 0,
+           1, 2)
+    expect(lbm.LBM_EINVAL, lbm.lbm_set_launch, lbm.KERNEL_ODD, 19, lbm.STORE_F32, 256, 1, 1,
+           1, 4)
 
 
 def test_header_compiles_as_c_and_cxx(tmp_path):

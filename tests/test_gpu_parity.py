@@ -944,6 +944,42 @@ def test_pipelined_odd_kernel_is_bitwise_identical():
 
 
 @pytest.mark.parametrize("q,kind,storage", [(19, lbm.COLL_TRT, lbm.STORE_F32),
+                                            (19, lbm.COLL_TRT, lbm.STORE_F64),
+                                            (27, lbm.COLL_CM, lbm.STORE_F16DEV)])
+def test_residency_caps_are_bitwise_identical(q, kind, storage):
+    """Capping the resident workgroups per CU (reserved LDS) changes where
+    and when tiles run, not the arithmetic: PDFs after odd and even step
+    counts are identical for every cap and block size, alone and batched."""
+    lab = inputs.random_mask((26, 22, 20), 0.3, seed=21, n_classes=3, class_fraction=0.5)
+    coll, bs, _ = _params(q, kind, 0.7, (1e-5, 0, 0), CLASSES)
+    dev_exp = 14 if storage == lbm.STORE_F16DEV else 0
+    old = [lbm.lbm_get_launch(k, q, storage, full=True) for k in (0, 1)]
+    out = []
+    try:
+        for block, g in ((256, 0), (256, 2), (256, 4), (128, 3), (64, 16)):
+            for k in (0, 1):
+                b0, x0, _, c0, _ = old[k]
+                lbm.lbm_set_launch(k, q, storage, block, x0, 0, c0, g)
+            sols = []
+            for j, sub in enumerate((lab, lab[:, 1:, :])):
+                d = lbm.SparseDomain(sub, 3, q, lbm.ORDER_BLOCKED)
+                d.compact_runs()
+                s = lbm.Solver(d, storage, dev_exp)
+                _upload(s, _random_state(q, d.n_fluid, seed=j + 31), dev_exp)
+                sols.append(s)
+            sols[0].step(4, coll, bs)
+            lbm.lbm_step_batch([s.state for s in sols], [coll, coll], [bs, bs], 5)
+            torch.cuda.synchronize()
+            out.append([s.pdf.clone() for s in sols])
+    finally:
+        for k in (0, 1):
+            lbm.lbm_set_launch(k, q, storage, *old[k])
+    for run in out[1:]:
+        for a, b in zip(out[0], run):
+            assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("q,kind,storage", [(19, lbm.COLL_TRT, lbm.STORE_F32),
                                             (19, lbm.COLL_SRT, lbm.STORE_F16DEV),
                                             (19, lbm.COLL_TRT, lbm.STORE_F64),
                                             (27, lbm.COLL_CUMULANT, lbm.STORE_BF16DEV)])

@@ -60,8 +60,8 @@ def test_serving_permeability_vs_oracle(storage, limit):
 
 
 def test_tuner_installs_a_measured_configuration(tmp_path):
-    """The tuner times every (block, XCD order, cells per thread) candidate
-    on a real solve, installs the fastest and caches it."""
+    """The tuner times every (block, XCD order, cells per thread, residency
+    cap) candidate on a real solve, installs the fastest and caches it."""
     from paper_2408_06880_amd import autotune
     lab, per, info = inputs.workload_c1(0.6, L=96, seed=5)
     dom = lbm.SparseDomain(lab, per, 19, lbm.ORDER_BLOCKED)
@@ -73,11 +73,11 @@ def test_tuner_installs_a_measured_configuration(tmp_path):
     try:
         path = str(tmp_path / "launch.json")
         res = autotune.tune_solver(sol, coll, cache_path=path, steps=3)
-        for k, n in ((0, 6), (1, 12)):
-            (b, x, c), timings = res[k]
-            assert len(timings) == n and min(timings.values()) == timings[(b, x, c)]
+        for k, n in ((0, 24), (1, 48)):
+            (b, x, c, g), timings = res[k]
+            assert len(timings) == n and min(timings.values()) == timings[(b, x, c, g)]
             got = lbm.lbm_get_launch(k, 19, lbm.STORE_F32, full=True)
-            assert (got[0], got[1], got[3]) == (b, x, c)
+            assert (got[0], got[1], got[3], got[4]) == (b, x, c, g)
         assert autotune.apply(path, 19, lbm.STORE_F32, dom.n_fluid) == 2
     finally:
         for k, cfg in zip((0, 1), old):
