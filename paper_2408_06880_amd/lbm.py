@@ -518,6 +518,53 @@ class Solver:
     def reduce(self, coll, stream=None, check=True):
         return lbm_reduce(self.state, coll, self._red_ws, stream, check)
 
+    _CKPT_LAYOUT = ("nx", "ny", "nz", "periodic", "q", "order", "align", "n_fluid", "stride",
+                    "n_links")
+
+    def checkpoint(self, path, stream=None):
+        """Write the solve to `path` (.npz, no pickled objects): layout,
+        storage, scale exponent, step count and the raw PDF-list bytes, plus
+        a digest of the fluid list that identifies the geometry.  Waits for
+        `stream` (default: the current one)."""
+        import hashlib
+
+        import numpy as np
+        import torch
+        (stream or torch.cuda.current_stream()).synchronize()
+        lay = self.state.layout
+        meta = np.array([getattr(lay, f) for f in self._CKPT_LAYOUT] +
+                        [self.storage, int(self.state.dev_exp), self.t], dtype=np.int64)
+        cells = self.domain.cells[:self.domain.n_fluid].cpu().numpy()
+        digest = np.frombuffer(hashlib.sha256(cells.tobytes()).digest(), dtype=np.uint8)
+        raw = self.pdf.view(torch.uint8).cpu().numpy()
+        with open(path, "wb") as f:
+            np.savez(f, meta=meta, cells_sha256=digest, pdf=raw)
+
+    def restore(self, path):
+        """Load a checkpoint written by checkpoint() for the same geometry
+        and storage: the PDF-list and the step count are replaced, so the
+        solve continues bit for bit where it was saved (either parity)."""
+        import hashlib
+
+        import numpy as np
+        import torch
+        with np.load(path, allow_pickle=False) as z:
+            meta, digest, raw = z["meta"], z["cells_sha256"], z["pdf"]
+        lay = self.state.layout
+        want = [getattr(lay, f) for f in self._CKPT_LAYOUT] + [self.storage,
+                                                                  int(self.state.dev_exp)]
+        if meta.shape != (len(want) + 1,) or [int(v) for v in meta[:-1]] != want:
+            raise ValueError("checkpoint layout, storage or scale differs from this solve")
+        cells = self.domain.cells[:self.domain.n_fluid].cpu().numpy()
+        if hashlib.sha256(cells.tobytes()).digest() != digest.tobytes():
+            raise ValueError("checkpoint was taken on a different geometry")
+        dst = self.pdf.view(torch.uint8)
+        if raw.shape != (dst.numel(),):
+            raise ValueError("checkpoint PDF-list size differs from this solve")
+        dst.copy_(torch.from_numpy(raw))
+        torch.cuda.current_stream().synchronize()
+        self.state.t = int(meta[-1])
+
     def device_bytes(self):
         """Bytes of the device buffers this solver holds (not the domain's)."""
         bufs = (self.pdf, self._red_ws, getattr(self, "_spare", None))

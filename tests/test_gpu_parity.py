@@ -827,6 +827,50 @@ def test_runs_without_int32_full_size_packing(packing256):
     assert torch.equal(a.pdf, b.pdf)
 
 
+@pytest.mark.parametrize("storage", [lbm.STORE_F64, lbm.STORE_F16DEV])
+def test_checkpoint_resume_is_bitwise(tmp_path, storage):
+    """A solve written at odd or even t and restored into a solver on a
+    rebuilt domain continues bit for bit like the uninterrupted one (links
+    and body force included); a different storage or geometry is refused."""
+    lab = inputs.random_mask((27, 25, 23), 0.3, seed=41, n_classes=3, class_fraction=0.5)
+    coll, bs, _ = _params(19, lbm.COLL_TRT, 0.7, (1e-5, 0, 0), CLASSES)
+    dev_exp = 14 if storage == lbm.STORE_F16DEV else 0
+
+    def domain(mask):
+        d = lbm.SparseDomain(mask, 3, 19, lbm.ORDER_BLOCKED)
+        d.compact_runs(drop_index=True)
+        return d
+
+    a = lbm.Solver(domain(lab), storage, dev_exp)
+    _upload(a, _random_state(19, a.domain.n_fluid, seed=5), dev_exp)
+    paths = {}
+    for t in (5, 8):
+        a.step(t - a.t, coll, bs)
+        paths[t] = str(tmp_path / f"t{t}.npz")
+        a.checkpoint(paths[t])
+    a.step(13 - a.t, coll, bs)
+    torch.cuda.synchronize()
+    for t in (5, 8):
+        b = lbm.Solver(domain(lab), storage, dev_exp)
+        b.init()
+        b.restore(paths[t])
+        assert b.t == t
+        b.step(13 - t, coll, bs)
+        torch.cuda.synchronize()
+        assert torch.equal(a.pdf, b.pdf)
+    other = lbm.STORE_F32 if storage == lbm.STORE_F64 else lbm.STORE_BF16DEV
+    with pytest.raises(ValueError):
+        lbm.Solver(a.domain, other, dev_exp).restore(paths[5])
+    moved = lab.copy()
+    fl = np.flatnonzero(moved == 0)
+    moved.flat[fl[0]], moved.flat[fl[-1]] = 1, 1
+    moved.flat[np.flatnonzero(lab == 1)[:2]] = 0      # same fluid count, other cells
+    d2 = domain(moved)
+    if d2.n_fluid == a.domain.n_fluid and d2.stride == a.domain.stride:
+        with pytest.raises(ValueError):
+            lbm.Solver(d2, storage, dev_exp).restore(paths[5])
+
+
 # ------------------------------------------------------------ pull scheme
 @pytest.mark.parametrize("compact,kind", [(False, lbm.COLL_TRT), (True, lbm.COLL_TRT),
                                           (False, lbm.COLL_MRT)])
