@@ -122,7 +122,8 @@ uint64_t lbm_build_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t o
  *                      i*S + m if the upstream cell x_k - c_i (wrapped on
  *                      periodic axes) is fluid with list position m, else
  *                      opp(i)*S + k; padding k in [n_fluid, S) gets
- *                      opp(i)*S + k (in bounds, never used);
+ *                      opp(i)*S + k (in bounds; no step gathers through
+ *                      a padding entry);
  *               links  device int32[2*n_links] (may be NULL iff n_links==0):
  *                      pairs (opp(i)*S + k, i | class << 8) for every
  *                      upstream cell with label 2 + class, ordered by (k, i).
@@ -148,8 +149,9 @@ typedef struct {
                          /* the same index, or NULL; when set, index reads use  */
                          /* it and fall back to `index` for escaped entries     */
   const void* runs;      /* device, run-compressed index-list (lbm_compress_runs)*/
-                         /* of the same index, or NULL; when set, odd steps read */
-                         /* it instead of index16 and index                     */
+                         /* of the same index, or NULL; when set, odd steps and  */
+                         /* moments/reductions at odd t read it instead of       */
+                         /* index16 and index                                    */
   const int32_t* links;  /* device, 2*n_links or NULL when n_links == 0        */
   int64_t t;             /* steps taken. t even: populations in natural slots  */
 } lbm_state;
