@@ -871,6 +871,57 @@ def test_checkpoint_resume_is_bitwise(tmp_path, storage):
             lbm.Solver(d2, storage, dev_exp).restore(paths[5])
 
 
+def test_largest_solve_below_the_int32_position_limit():
+    """A fully fluid periodic 480^3 box (110.6 M cells, q*S within 3 % of
+    2^31, 8.4 GB of FP32 PDFs): one odd step on a random state, checked on
+    sampled cells (including the last list positions, whose slots in the
+    last direction block lie near 2^31) against the oracle's collision of
+    the pulled populations.  A 500^3 box exceeds the limit and is refused
+    with LBM_ERANGE."""
+    n, q = 480, 19
+    lab = np.zeros((n, n, n), np.uint8)
+    dom = lbm.SparseDomain(lab, 7, q, lbm.ORDER_BLOCKED)
+    S, nf = dom.stride, dom.n_fluid
+    assert nf == n ** 3 and 0.97 * 2 ** 31 < q * S < 2 ** 31
+    dom.compact_runs()
+    sol = lbm.Solver(dom, lbm.STORE_F32)
+    _, w, _ = oracle.stencil(q)
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    pdf = sol.pdf.view(q, S)
+    pdf.copy_(torch.tensor(w, dtype=torch.float32, device="cuda")[:, None]
+              * (1 + 0.05 * torch.rand((q, S), generator=gen, device="cuda")))
+    rng = np.random.default_rng(3)
+    ks = np.concatenate([rng.integers(0, nf, 48), np.arange(nf - 16, nf)])
+    kt = torch.from_numpy(ks).cuda()
+    lin = dom.cells[kt].long().cpu().numpy()
+    inv = torch.empty(nf, dtype=torch.int64, device="cuda")
+    inv[dom.cells[:nf].long()] = torch.arange(nf, device="cuda")
+    c, _, opp = oracle.stencil(q)
+    x, y, z = lin % n, (lin // n) % n, lin // (n * n)
+    pulled = np.empty((len(ks), q))
+    for i in range(q):
+        up = ((x - c[i, 0]) % n) + n * (((y - c[i, 1]) % n) + n * ((z - c[i, 2]) % n))
+        m = inv[torch.from_numpy(up).cuda()]
+        pulled[:, i] = pdf[i, m].double().cpu().numpy()
+    coll = lbm.collision(lbm.COLL_TRT, tau=0.8, force=(1e-5, 0, 0))
+    p = oracle.params(q=q, kind=oracle.TRT, tau=0.8, magic=3 / 16, force=(1e-5, 0, 0))
+    want = oracle.collide(p, pulled)
+    del inv
+    sol.step(1, coll)
+    got = np.empty_like(want)
+    idx = dom.index.view(q - 1, S)
+    for j in range(q):
+        pos = kt if j == 0 else idx[opp[j] - 1, kt].long()
+        got[:, j] = sol.pdf[pos].double().cpu().numpy()
+    _say("largest solve: max abs diff", np.max(np.abs(got - want)))
+    assert np.max(np.abs(got - want)) < 1e-6
+    del sol, dom, pdf, idx
+    torch.cuda.empty_cache()
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.SparseDomain(np.zeros((500, 500, 500), np.uint8), 7, q, lbm.ORDER_BLOCKED)
+    assert e.value.code == lbm.LBM_ERANGE
+
+
 # ------------------------------------------------------------ pull scheme
 @pytest.mark.parametrize("compact,kind", [(False, lbm.COLL_TRT), (True, lbm.COLL_TRT),
                                           (False, lbm.COLL_MRT)])
