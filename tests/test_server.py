@@ -184,3 +184,28 @@ def test_builds_overlap_steps_and_never_wait_while_solves_are_active():
         out[gate] = (st.waits_while_busy, met["makespan_s"])
     assert out[True][0] == 0 and out[False][0] > 0
     assert out[True][1] < out[False][1]
+
+
+def test_admission_counts_the_build_transient():
+    """A request whose held bytes fit but whose build transient does not
+    waits for memory (or is rejected when it can never fit)."""
+
+    class Transient(server.MockStepper):
+        def transient_bytes(self, r):
+            return self.bytes_needed(r)          # the build needs as much again
+
+    trace = [server.Request(rid=i, arrival=0.0, L=32, phi=0.5, seed=i, tau=0.8) for i in range(3)]
+    one = int(0.5 * 32 ** 3) * 112
+    st = Transient(rate_flups=5e9)
+    srv = server.Server(st, 3 * one, K=100, clock=st.clock, sleep=st.sleep)
+    res, met = srv.run(trace)
+    assert met["completed"] == 3
+    # 3 x held would fit, but each admission also needs a transient of one
+    # solve: at most two solves are resident at a time
+    peak = max(len([r for r in res if r.admitted <= t < r.finished]) for t in
+               sorted({r.admitted for r in res}))
+    assert peak <= 2
+    st = Transient(rate_flups=5e9)
+    res, met = server.Server(st, one + one // 2, K=100, clock=st.clock,
+                             sleep=st.sleep).run(trace[:1])
+    assert res[0].error and met["completed"] == 0
