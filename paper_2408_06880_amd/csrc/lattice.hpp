@@ -106,9 +106,10 @@ struct Store<ST_BF16DEV> {
 
 // ---------------------------------------------------------------------------
 // Launch arguments.  One launch advances up to kMaxSeg independent solves
-// ("segments"); segment s owns workgroup tiles [tile0_s, tile0_{s+1}).
+// ("segments"); segment s owns workgroup tiles [tile0_s, tile0_{s+1}).  The
+// table travels in the kernel arguments (64 segments: about 10 KB).
 // ---------------------------------------------------------------------------
-constexpr int kMaxSeg = 16;
+constexpr int kMaxSeg = 64;
 
 // Compact index-list: tiles of kTile16 list positions.
 constexpr uint32_t kTile16 = 256;
@@ -171,11 +172,18 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t v, uint32_t n) {
   return x * per + (x < rem ? x : rem) + local;
 }
 
+// Segment of a tile: the last segment whose first tile is not after it
+// (binary search; first tiles do not decrease with the segment number).
 __device__ __forceinline__ int seg_of(const StepArgs& a, uint32_t tile) {
-  int s = 0;
-  for (int j = 1; j < a.nseg; ++j)
-    if (a.seg[j].tile0 <= tile) s = j;
-  return s;
+  int lo = 0, hi = a.nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.seg[mid].tile0 <= tile)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
 }
 
 }  // namespace lbm

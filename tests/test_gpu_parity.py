@@ -763,6 +763,43 @@ def test_runs_batch_mixes_index_forms():
         assert torch.equal(x, y)
 
 
+def test_batch_of_many_solves_matches_each_alone():
+    """40 small solves of different sizes, index forms and boundary classes
+    (one launch carries up to 64): batched steps and batched FP64
+    reductions equal each solve stepped and reduced alone, bit for bit."""
+    coll, bs, _ = _params(19, lbm.COLL_TRT, 0.7, (1e-5, 0, 0), CLASSES)
+    labs = [inputs.random_mask((6 + j % 5, 7 + j % 3, 5 + j % 4), 0.3, seed=200 + j,
+                               n_classes=3 if j % 3 == 0 else 0, class_fraction=0.5)
+            for j in range(40)]
+    out = []
+    for batched in (False, True):
+        sols = []
+        for j, lab in enumerate(labs):
+            dom = lbm.SparseDomain(lab, 3 if j % 3 == 0 else 7, 19, lbm.ORDER_BLOCKED)
+            if j % 4 == 1:
+                dom.compact()
+            elif j % 4 == 2:
+                dom.compact_runs(drop_index=True)
+            s = lbm.Solver(dom, lbm.STORE_F32)
+            _upload(s, _random_state(19, dom.n_fluid, seed=j + 50), 0)
+            sols.append(s)
+        if batched:
+            lbm.lbm_step_batch([s.state for s in sols], [coll] * 40, [bs] * 40, 5)
+            ws = torch.empty(sum(lbm.lbm_reduce_workspace_bytes(s.domain.layout) for s in sols),
+                             dtype=torch.uint8, device="cuda")
+            red = lbm.lbm_reduce_batch([s.state for s in sols], [coll] * 40, ws)
+        else:
+            for s in sols:
+                s.step(5, coll, bs)
+            red = [s.reduce(coll) for s in sols]
+        torch.cuda.synchronize()
+        out.append(([s.pdf.clone() for s in sols],
+                    [(r.mass, tuple(r.mom), r.n_fluid) for r in red]))
+    for a, b in zip(out[0][0], out[1][0]):
+        assert torch.equal(a, b)
+    assert out[0][1] == out[1][1]
+
+
 def test_runs_empty_and_single_cell():
     lab = np.ones((4, 4, 4), np.uint8)
     dom = lbm.SparseDomain(lab, 7, 19)
