@@ -54,7 +54,7 @@ typedef int32_t lbm_status;
 
 #define LBM_OK 0
 #define LBM_EINVAL (-1)    /* invalid argument                                  */
-#define LBM_ERANGE (-2)    /* q * stride does not fit int32 positions            */
+#define LBM_ERANGE (-2)    /* q * stride does not fit 32-bit positions           */
 #define LBM_ENOMEM (-3)    /* caller buffer / workspace too small                */
 #define LBM_EDEVICE (-4)   /* a HIP call failed                                  */
 #define LBM_EUNSTABLE (-5) /* a reduction saw NaN or Inf                          */
@@ -118,7 +118,8 @@ uint64_t lbm_build_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t o
  *             must be the plan's result for the same labels (unchanged in
  *             between); writes
  *               cells  device int32[n_fluid]: lin of the k-th fluid cell;
- *               index  device int32[(q-1)*stride]: element (i-1)*S + k =
+ *               index  device int32[(q-1)*stride] holding unsigned 32-bit
+ *                      PDF positions (q*S < 2^32): element (i-1)*S + k =
  *                      i*S + m if the upstream cell x_k - c_i (wrapped on
  *                      periodic axes) is fluid with list position m, else
  *                      opp(i)*S + k; padding k in [n_fluid, S) gets
@@ -127,7 +128,7 @@ uint64_t lbm_build_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t o
  *               links  device int32[2*n_links] (may be NULL iff n_links==0):
  *                      pairs (opp(i)*S + k, i | class << 8) for every
  *                      upstream cell with label 2 + class, ordered by (k, i).
- * Errors: LBM_EINVAL (sizes, q, order, align), LBM_ERANGE (q*S >= 2^31),
+ * Errors: LBM_EINVAL (sizes, q, order, align), LBM_ERANGE (q*S >= 2^32),
  *         LBM_EDEVICE. */
 lbm_status lbm_build_sparse(const uint8_t* labels, int32_t nx, int32_t ny, int32_t nz,
                             uint32_t periodic, int32_t q, int32_t order, int32_t align,

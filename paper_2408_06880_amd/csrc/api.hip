@@ -95,8 +95,8 @@ lbm_status check_layout(const lbm_layout& L) {
   if (L.n_fluid < 0 || L.stride < L.n_fluid || L.n_links < 0)
     return fail(LBM_EINVAL, "inconsistent layout sizes (n_fluid %lld, stride %lld)",
                 (long long)L.n_fluid, (long long)L.stride);
-  if ((int64_t)L.q * L.stride >= (int64_t)1 << 31)
-    return fail(LBM_ERANGE, "q*stride = %lld does not fit int32 positions",
+  if ((int64_t)L.q * L.stride >= (int64_t)1 << 32)
+    return fail(LBM_ERANGE, "q*stride = %lld does not fit 32-bit positions",
                 (long long)L.q * L.stride);
   return LBM_OK;
 }

@@ -147,7 +147,7 @@ __device__ __forceinline__ uint32_t run_pos(const Seg& g, int q, int i, uint32_t
   for (int d = 1; d < i; ++d) vb += (uint32_t)__popcll(mk[d - 1]);
   const uint64_t upto = lane == kRunWave - 1 ? ~0ull : ((2ull << lane) - 1ull);
   const uint32_t r = (uint32_t)__popcll(mk[i - 1] & upto) - 1u;
-  return (uint32_t)(g.rval[vb + r] + (int32_t)lane);
+  return (uint32_t)g.rval[vb + r] + lane;
 }
 
 // Post-collision deviations of cell k at the current time in natural order.

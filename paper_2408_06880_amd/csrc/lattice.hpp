@@ -159,7 +159,7 @@ __device__ __forceinline__ uint32_t pos16(const Seg& g, int q, int i, int oi, ui
   const int32_t b = g.base16[(size_t)t16 * (q - 1) + (i - 1)];
   if (o >= kEscape16)
     return o == kBounce16 ? (uint32_t)oi * g.S + k : (uint32_t)g.idx[(size_t)(i - 1) * g.S + k];
-  return (uint32_t)((int32_t)((uint32_t)i * g.S + k) + b + (int32_t)o);
+  return (uint32_t)i * g.S + k + (uint32_t)b + (uint32_t)o;
 }
 
 // XCD-aware tile order.  Workgroups are dispatched round-robin over the 8

@@ -12,10 +12,10 @@ namespace lbm {
 
 // Whether the calling lane starts a run: lane 0 always does, a lane inside
 // the list does when its entry p is not its left neighbour's plus one, a
-// lane past the list end never does.
-__device__ __forceinline__ bool run_start(int32_t p, uint32_t lane, bool in_list) {
-  const int32_t prev = __shfl_up(p, 1, (int)kRunWave);
-  return lane == 0 || (in_list && p != prev + 1);
+// lane past the list end never does.  Entries are unsigned positions.
+__device__ __forceinline__ bool run_start(uint32_t p, uint32_t lane, bool in_list) {
+  const uint32_t prev = (uint32_t)__shfl_up((int)p, 1, (int)kRunWave);
+  return lane == 0 || (in_list && p != prev + 1u);
 }
 
 template <int Q>
@@ -27,7 +27,7 @@ __global__ __launch_bounds__(256) void k_runs_mask(const int32_t* __restrict__ i
   const uint32_t lane = threadIdx.x & (kRunWave - 1), k = w * kRunWave + lane;
   uint32_t total = 0;
   for (int i = 1; i < Q; ++i) {
-    const int32_t p = k < S ? index[(size_t)(i - 1) * S + k] : 0;
+    const uint32_t p = k < S ? (uint32_t)index[(size_t)(i - 1) * S + k] : 0u;
     const uint64_t m = __ballot(run_start(p, lane, k < S));
     if (lane == 0) mask[(size_t)w * (Q - 1) + (i - 1)] = m;
     total += (uint32_t)__popcll(m);
@@ -44,14 +44,14 @@ __global__ __launch_bounds__(256) void k_runs_emit(const int32_t* __restrict__ i
   const uint32_t lane = threadIdx.x & (kRunWave - 1), k = w * kRunWave + lane;
   uint32_t o = voff[w];
   for (int i = 1; i < Q; ++i) {
-    const int32_t p = k < S ? index[(size_t)(i - 1) * S + k] : 0;
+    const uint32_t p = k < S ? (uint32_t)index[(size_t)(i - 1) * S + k] : 0u;
     const bool st = run_start(p, lane, k < S);
     const uint64_t m = __ballot(st);
     if (st) {
       // number of run starts below this lane
       const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-      val[o + r] = p - (int32_t)lane;
+      val[o + r] = (int32_t)(p - lane);
     }
     o += (uint32_t)__popcll(m);
   }

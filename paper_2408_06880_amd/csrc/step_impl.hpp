@@ -108,7 +108,7 @@ __device__ __forceinline__ void run_positions(const Seg& g, uint32_t k, uint32_t
     const uint64_t m1 = m >> 1;
     const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m1 >> 32),
                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)m1, 0u));
-    pos[i] = (uint32_t)(val[vb + r] + (int32_t)lane);
+    pos[i] = (uint32_t)val[vb + r] + lane;
     vb += (uint32_t)__builtin_popcountll(m);
   }
 }
@@ -152,7 +152,7 @@ __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU))) void k_aa_step(const
       bool esc = false;
 #pragma unroll
       for (int i = 1; i < Q; ++i) {
-        const uint32_t fl = (uint32_t)((int32_t)((uint32_t)i * S + k) + b[i] + (int32_t)o[i]);
+        const uint32_t fl = (uint32_t)i * S + k + (uint32_t)b[i] + o[i];
         const uint32_t bb = (uint32_t)opp(i) * S + k;
         const uint32_t m = 0u - (uint32_t)(o[i] == kBounce16);  // all ones: bounce-back
         pos[i] = (fl & ~m) | (bb & m);
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(256) void k_odd_pipe(const StepArgs a) {
         bool esc = false;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-          const uint32_t fl = (uint32_t)((int32_t)((uint32_t)i * S + k) + b[i] + (int32_t)o[i]);
+          const uint32_t fl = (uint32_t)i * S + k + (uint32_t)b[i] + o[i];
           const uint32_t bb = (uint32_t)opp(i) * S + k;
           const uint32_t m = 0u - (uint32_t)(o[i] == kBounce16);
           pos[i] = (fl & ~m) | (bb & m);

@@ -95,7 +95,17 @@ def test_invalid_arguments_rejected_on_host():
     st = _fake_state(storage=lbm.STORE_F16DEV)
     st.dev_exp = 30
     expect(lbm.LBM_EINVAL, lbm.lbm_step, st, 1, lbm.collision(), None, 0)
-    big = _fake_state(nf=200_000_000, S=200_000_000)
+    # positions are unsigned 32-bit: 19 * S between 2^31 and 2^32 is accepted
+    # (the size query below gets past validation), from 2^32 on it is not
+    need = ctypes.c_uint64(0)
+    mid = _fake_state(nf=200_000_000, S=200_000_000).layout
+    rc = lbm.load().lbm_compress_runs(ctypes.byref(mid), ctypes.c_void_p(16),
+                                      ctypes.c_void_p(16), 0, ctypes.byref(need), None)
+    assert rc == lbm.LBM_ENOMEM and need.value == lbm.lbm_runs_header_bytes(mid)
+    big = _fake_state(nf=230_000_000, S=230_000_000)   # 19 * S >= 2^32
+    rc = lbm.load().lbm_compress_runs(ctypes.byref(big.layout), ctypes.c_void_p(16),
+                                      ctypes.c_void_p(16), 0, ctypes.byref(need), None)
+    assert rc == lbm.LBM_ERANGE
     expect(lbm.LBM_ERANGE, lbm.lbm_step, big, 1, lbm.collision(), None, 0)
     expect(lbm.LBM_EINVAL, lbm.lbm_step, _fake_state(), -1, lbm.collision(), None, 0)
     expect(lbm.LBM_EINVAL, lbm.lbm_set_launch, lbm.KERNEL_ODD, 19, lbm.STORE_F32, 100, 1)

@@ -908,25 +908,26 @@ def test_checkpoint_resume_is_bitwise(tmp_path, storage):
             lbm.Solver(d2, storage, dev_exp).restore(paths[5])
 
 
-def test_largest_solve_below_the_int32_position_limit():
-    """A fully fluid periodic 480^3 box (110.6 M cells, q*S within 3 % of
-    2^31, 8.4 GB of FP32 PDFs): one odd step on a random state, checked on
-    sampled cells (including the last list positions, whose slots in the
-    last direction block lie near 2^31) against the oracle's collision of
-    the pulled populations.  A 500^3 box exceeds the limit and is refused
-    with LBM_ERANGE."""
-    n, q = 480, 19
+def test_large_solve_with_positions_beyond_2_31():
+    """A fully fluid periodic 600^3 box (216 M cells, 16.4 GB of FP32 PDFs):
+    its positions run past 2^31 (q*S = 4.1e9 < 2^32, unsigned 32-bit).  One
+    odd step on a random state through the run form, checked on sampled
+    cells (including the last list positions, whose slots in the last
+    direction blocks lie above 2^31) against the oracle's collision of the
+    pulled populations.  A 610^3 box needs q*S >= 2^32 and is refused with
+    LBM_ERANGE."""
+    n, q = 600, 19
     lab = np.zeros((n, n, n), np.uint8)
     dom = lbm.SparseDomain(lab, 7, q, lbm.ORDER_BLOCKED)
     S, nf = dom.stride, dom.n_fluid
-    assert nf == n ** 3 and 0.97 * 2 ** 31 < q * S < 2 ** 31
+    assert nf == n ** 3 and 2 ** 31 < q * S < 2 ** 32
     dom.compact_runs()
     sol = lbm.Solver(dom, lbm.STORE_F32)
     _, w, _ = oracle.stencil(q)
     gen = torch.Generator(device="cuda").manual_seed(7)
     pdf = sol.pdf.view(q, S)
-    pdf.copy_(torch.tensor(w, dtype=torch.float32, device="cuda")[:, None]
-              * (1 + 0.05 * torch.rand((q, S), generator=gen, device="cuda")))
+    for i in range(q):
+        pdf[i].copy_(float(w[i]) * (1 + 0.05 * torch.rand(S, generator=gen, device="cuda")))
     rng = np.random.default_rng(3)
     ks = np.concatenate([rng.integers(0, nf, 48), np.arange(nf - 16, nf)])
     kt = torch.from_numpy(ks).cuda()
@@ -947,15 +948,18 @@ def test_largest_solve_below_the_int32_position_limit():
     sol.step(1, coll)
     got = np.empty_like(want)
     idx = dom.index.view(q - 1, S)
+    above = 0
     for j in range(q):
-        pos = kt if j == 0 else idx[opp[j] - 1, kt].long()
+        pos = kt if j == 0 else idx[opp[j] - 1, kt].long() & 0xFFFFFFFF
+        above += int((pos >= 2 ** 31).sum())
         got[:, j] = sol.pdf[pos].double().cpu().numpy()
-    _say("largest solve: max abs diff", np.max(np.abs(got - want)))
+    assert above > 0
+    _say("large solve: max abs diff", np.max(np.abs(got - want)), "positions above 2^31:", above)
     assert np.max(np.abs(got - want)) < 1e-6
     del sol, dom, pdf, idx
     torch.cuda.empty_cache()
     with pytest.raises(lbm.LbmError) as e:
-        lbm.SparseDomain(np.zeros((500, 500, 500), np.uint8), 7, q, lbm.ORDER_BLOCKED)
+        lbm.SparseDomain(np.zeros((610, 610, 610), np.uint8), 7, q, lbm.ORDER_BLOCKED)
     assert e.value.code == lbm.LBM_ERANGE
 
 
