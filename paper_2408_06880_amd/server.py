@@ -148,7 +148,7 @@ class Server:
                 if (self.target_cells is not None and (active or admit) and
                         cells + self.stepper.cells_estimate(r) > self.target_cells):
                     break
-                if (active or admit) and not self.stepper.ready(r):
+                if (active or admit) and not getattr(self.stepper, "ready", lambda _r: True)(r):
                     break
                 queue.popleft()
                 results[r.rid].admitted = self.clock() - t0
@@ -162,21 +162,35 @@ class Server:
                         self.sleep(wait)
                 continue
 
-            def start(r, need):
-                handle = self.stepper.build(r)
-                res = results[r.rid]
-                res.n_fluid = self.stepper.n_fluid(handle)
-                return {"req": r, "res": res, "handle": handle, "bytes": need, "jx": [],
-                        "refined": False}
+            def start(batch):
+                """Build the admitted requests; one that cannot be built
+                fails alone and gives its memory back."""
+                nonlocal used
+                out = []
+                for r, need in batch:
+                    res = results[r.rid]
+                    try:
+                        handle = self.stepper.build(r)
+                    except Exception as e:   # noqa: BLE001 (reported per request)
+                        res.error = f"build failed: {e}"
+                        res.finished = self.clock() - t0
+                        used -= need
+                        continue
+                    res.n_fluid = self.stepper.n_fluid(handle)
+                    out.append({"req": r, "res": res, "handle": handle, "bytes": need,
+                                "jx": [], "refined": False})
+                return out
 
             if not active:   # nothing to overlap with: build, then step
-                active = [start(r, need) for r, need in admit]
+                active = start(admit)
                 admit = []
+                if not active:
+                    continue
             # one round: K lockstep steps for every active solve, with the
             # builds of newly admitted solves overlapping them
             tb = self.clock()
             self.stepper.step([a["handle"] for a in active], self.K)
-            joined = [start(r, need) for r, need in admit]
+            joined = start(admit)
             red = self.stepper.reduce([a["handle"] for a in active])
             busy += self.clock() - tb
             keep = []

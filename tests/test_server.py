@@ -209,3 +209,43 @@ def test_admission_counts_the_build_transient():
     res, met = server.Server(st, one + one // 2, K=100, clock=st.clock,
                              sleep=st.sleep).run(trace[:1])
     assert res[0].error and met["completed"] == 0
+
+
+def test_failed_build_fails_only_that_request():
+    """A request whose build raises (with or without other solves active)
+    gets an error and its memory back; the others are served."""
+
+    class BuildFails(server.MockStepper):
+        def build(self, r):
+            if r.rid in (0, 4):
+                raise RuntimeError("cannot build")
+            return super().build(r)
+
+    trace = server.make_trace(8, 20.0, seed=9, L_range=(32, 48))
+    st = BuildFails(rate_flups=5e9)
+    budget = 1 << 40
+    srv = server.Server(st, budget, K=100, clock=st.clock, sleep=st.sleep)
+    res, met = srv.run(trace)
+    assert sorted(r.rid for r in res if r.error) == [0, 4]
+    assert all("build failed" in r.error for r in res if r.error)
+    assert met["completed"] == 6 and met["converged"] == 6
+
+
+def test_stepper_without_readiness_query_is_served():
+    """ready() and transient_bytes() are optional parts of a stepper."""
+
+    class Minimal:
+        def __init__(self, inner):
+            self._inner = inner
+
+        def __getattr__(self, name):
+            if name in ("ready", "transient_bytes"):
+                raise AttributeError(name)
+            return getattr(self._inner, name)
+
+    st = server.MockStepper(rate_flups=5e9)
+    wrapped = Minimal(st)
+    assert not hasattr(wrapped, "ready") and not hasattr(wrapped, "transient_bytes")
+    res, met = server.Server(wrapped, 1 << 40, K=100, clock=st.clock, sleep=st.sleep).run(
+        server.make_trace(4, 20.0, seed=2, L_range=(32, 40)))
+    assert met["completed"] == 4
