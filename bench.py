@@ -378,6 +378,10 @@ def main():
     ap.add_argument("--even-cells", type=int, default=0, choices=[0, 1, 2],
                     help="cells per thread of the even-step kernel (0: the library's "
                          "default, two for 16-bit storage)")
+    ap.add_argument("--odd-block", type=int, default=None, choices=[64, 128, 256],
+                    help="workgroup size of the odd-step kernel (default: the library's table)")
+    ap.add_argument("--even-block", type=int, default=None, choices=[64, 128, 256],
+                    help="the same for the even-step kernel")
     ap.add_argument("--odd-groups", type=int, default=None,
                     help="resident workgroups per CU of the odd-step kernel (0: uncapped; "
                          "default: the library's table)")
@@ -503,11 +507,14 @@ def main():
         cfg = list(lbm.lbm_get_launch(lbm.KERNEL_EVEN, q, storage, full=True))
         cfg[3] = args.even_cells
         lbm.lbm_set_launch(lbm.KERNEL_EVEN, q, storage, *cfg)
-    for kern, g in ((lbm.KERNEL_ODD, args.odd_groups), (lbm.KERNEL_EVEN, args.even_groups)):
+    for kern, blk, g in ((lbm.KERNEL_ODD, args.odd_block, args.odd_groups),
+                         (lbm.KERNEL_EVEN, args.even_block, args.even_groups)):
+        cfg = list(lbm.lbm_get_launch(kern, q, storage, full=True))
+        if blk is not None:
+            cfg[0] = blk
         if g is not None:
-            cfg = list(lbm.lbm_get_launch(kern, q, storage, full=True))
             cfg[4] = g
-            lbm.lbm_set_launch(kern, q, storage, *cfg)
+        lbm.lbm_set_launch(kern, q, storage, *cfg)
     sol = lbm.Solver(dom, storage, dev_exp)
     solve_bytes = dom.device_bytes() + sol.device_bytes()
     if vessel:

@@ -54,8 +54,10 @@ void launch_defaults() {
   // one otherwise.  Fewer resident workgroups than registers allow stream
   // better for D3Q19 on the 256^3 packing (block 256): FP32 and FP32-dev
   // odd step at 4 per CU (FP32 360 -> 355 us), even step at 3 (FP32-dev
-  // 262 -> 253 us), FP64 even at 2 (565 -> 539 us); 16-bit storage, the
-  // FP64 odd step and the D3Q27 kernels run fastest uncapped.
+  // 262 -> 253 us); the FP64 even step with 64-thread workgroups, two cells
+  // per thread and 2 per CU (565 -> 516 us at porosity 0.6, 3-4 % faster
+  // than 256 threads at 2 per CU for porosities 0.4-0.95); 16-bit storage,
+  // the FP64 odd step and the D3Q27 kernels run fastest uncapped.
   for (int k = 0; k < 3; ++k)
     for (int qi = 0; qi < 2; ++qi)
       for (int st = 0; st < 5; ++st) {
@@ -67,7 +69,11 @@ void launch_defaults() {
         c.max_groups_per_cu = 0;
         if (qi == 0 && (st == LBM_STORE_F32 || st == LBM_STORE_F32DEV))
           c.max_groups_per_cu = k == LBM_KERNEL_ODD ? 4 : (k == LBM_KERNEL_EVEN ? 3 : 0);
-        if (qi == 0 && st == LBM_STORE_F64 && k == LBM_KERNEL_EVEN) c.max_groups_per_cu = 2;
+        if (qi == 0 && st == LBM_STORE_F64 && k == LBM_KERNEL_EVEN) {
+          c.block = 64;
+          c.cells_per_thread = 2;
+          c.max_groups_per_cu = 2;
+        }
       }
   g_launch_init = true;
 }
@@ -525,7 +531,7 @@ static lbm_status step_group(lbm_state* const* states, const lbm_collision* cons
   const int kind = colls[0]->kind;
   for (int32_t step = 0; step < n_steps; ++step) {
     const bool odd = (states[0]->t & 1) == 0;
-    const lbm_launch cfg = get_cfg(odd ? LBM_KERNEL_ODD : LBM_KERNEL_EVEN, q, storage);
+    lbm_launch cfg = get_cfg(odd ? LBM_KERNEL_ODD : LBM_KERNEL_EVEN, q, storage);
     for (int32_t j = 0; j < n; ++j) {
       lbm_status rc = link_update(states[j], bspecs ? bspecs[j] : nullptr, st);
       if (rc) return rc;
@@ -537,6 +543,9 @@ static lbm_status step_group(lbm_state* const* states, const lbm_collision* cons
     bool even_strides = true;
     for (int32_t j = 0; j < n; ++j) even_strides = even_strides && (states[j]->layout.stride % 2 == 0);
     const uint32_t cpt = (!odd && cfg.cells_per_thread == 2 && even_strides) ? 2 : 1;
+    // a residency cap chosen for the two-cell kernel does not carry over to
+    // its one-cell fallback
+    if (!odd && cfg.cells_per_thread == 2 && cpt == 1) cfg.max_groups_per_cu = 0;
     for (int form = IDX_I32; form <= IDX_RUN; ++form) {
       int32_t j = 0;
       while (j < n) {

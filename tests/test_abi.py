@@ -148,10 +148,11 @@ def test_launch_table_roundtrip():
     old = lbm.lbm_get_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F16DEV, full=True)
     assert old == (256, 0, 0, 2, 0)       # 16-bit storage: two cells per thread
     assert lbm.lbm_get_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F32, full=True) == (256, 0, 0, 1, 0)
-    # measured residency caps: D3Q19 FP32 and FP32-dev odd 4 and even 3, FP64 even 2
+    # measured residency caps: D3Q19 FP32 and FP32-dev odd 4 and even 3; FP64
+    # even step 64-thread workgroups, two cells per thread, 2 per CU
     assert lbm.lbm_get_launch(lbm.KERNEL_ODD, 19, lbm.STORE_F32, full=True) == (256, 1, 0, 1, 4)
     assert lbm.lbm_get_launch(lbm.KERNEL_EVEN, 19, lbm.STORE_F32, full=True) == (256, 0, 0, 1, 3)
-    assert lbm.lbm_get_launch(lbm.KERNEL_EVEN, 19, lbm.STORE_F64, full=True) == (256, 0, 0, 1, 2)
+    assert lbm.lbm_get_launch(lbm.KERNEL_EVEN, 19, lbm.STORE_F64, full=True) == (64, 0, 0, 2, 2)
     assert lbm.lbm_get_launch(lbm.KERNEL_ODD, 19, lbm.STORE_F64, full=True) == (256, 1, 0, 1, 0)
     assert lbm.lbm_get_launch(lbm.KERNEL_EVEN, 19, lbm.STORE_F32DEV, full=True) == (256, 0, 0, 1, 3)
     assert lbm.lbm_get_launch(lbm.KERNEL_ODD, 27, lbm.STORE_F32, full=True) == (256, 1, 0, 1, 0)

@@ -1079,6 +1079,30 @@ def test_pipelined_odd_kernel_is_bitwise_identical():
         assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("storage", [lbm.STORE_F64, lbm.STORE_F32, lbm.STORE_F16DEV])
+def test_default_launch_odd_and_even_strides_agree(storage):
+    """With the library's default launch table, an even stride (two cells
+    per thread where the table says so) and an odd one (the one-cell
+    fallback, without the two-cell kernel's residency cap) give the same
+    PDFs on the fluid cells, bit for bit."""
+    lab = inputs.random_mask((25, 23, 21), 0.3, seed=61, n_classes=3, class_fraction=0.5)
+    if np.count_nonzero(lab == 0) % 2 == 0:       # odd fluid count: odd stride at align 1
+        lab[np.unravel_index(np.flatnonzero(lab == 1)[0], lab.shape)] = 0
+    coll, bs, _ = _params(19, lbm.COLL_TRT, 0.7, (1e-5, 0, 0), CLASSES)
+    dev_exp = 14 if storage == lbm.STORE_F16DEV else 0
+    out = []
+    for align in (64, 1):
+        dom = lbm.SparseDomain(lab, 3, 19, lbm.ORDER_BLOCKED, align=align)
+        assert (dom.stride % 2 == 1) == (align == 1)
+        dom.compact_runs()
+        s = lbm.Solver(dom, storage, dev_exp)
+        _upload(s, _random_state(19, dom.n_fluid, seed=8), dev_exp)
+        s.step(6, coll, bs)
+        torch.cuda.synchronize()
+        out.append(s.pdf.view(19, -1)[:, :dom.n_fluid].clone())
+    assert torch.equal(out[0], out[1])
+
+
 @pytest.mark.parametrize("q,kind,storage", [(19, lbm.COLL_TRT, lbm.STORE_F32),
                                             (19, lbm.COLL_TRT, lbm.STORE_F64),
                                             (27, lbm.COLL_CM, lbm.STORE_F16DEV)])
