@@ -378,6 +378,9 @@ def main():
     ap.add_argument("--even-cells", type=int, default=0, choices=[0, 1, 2],
                     help="cells per thread of the even-step kernel (0: the library's "
                          "default, two for 16-bit storage)")
+    ap.add_argument("--tune", action="store_true",
+                    help="run the launch tuner on this solve first (untimed) and keep the "
+                         "fastest configurations")
     ap.add_argument("--odd-block", type=int, default=None, choices=[64, 128, 256],
                     help="workgroup size of the odd-step kernel (default: the library's table)")
     ap.add_argument("--even-block", type=int, default=None, choices=[64, 128, 256],
@@ -523,6 +526,12 @@ def main():
         kind = {"trt": lbm.COLL_TRT, "srt": lbm.COLL_SRT, "mrt": lbm.COLL_MRT,
                 "cumulant": lbm.COLL_CUMULANT, "cm": lbm.COLL_CM}[args.coll]
         coll = lbm.collision(kind, tau=args.tau, magic=magic, force=force, omega_bulk=1.19)
+    if args.tune:
+        from paper_2408_06880_amd import autotune
+        sol.init()
+        tuned = autotune.tune_solver(sol, coll, steps=8)
+        log("tuned launch (block, xcd, cells, groups): " +
+            ", ".join(f"{'odd' if k == 0 else 'even'} {v[0]}" for k, v in tuned.items()))
     sol.init()
     sol.step(args.warmup, coll, bs)
     torch.cuda.synchronize()
@@ -654,6 +663,7 @@ def main():
                    "scheme": args.scheme, "pipelined_odd": args.pipelined,
                    "even_cells_per_thread": lbm.lbm_get_launch(lbm.KERNEL_EVEN, q, storage,
                                                                full=True)[3],
+                   "tuned": args.tune,
                    "launch_odd": lbm.lbm_get_launch(lbm.KERNEL_ODD, q, storage, full=True),
                    "launch_even": lbm.lbm_get_launch(lbm.KERNEL_EVEN, q, storage, full=True),
                    "index_escaped_fraction": escaped,
