@@ -394,7 +394,8 @@ typedef struct {
  * 256; XCD-aware tile order for the odd kernel only; two cells per thread
  * for even steps in 16-bit storage; D3Q19 FP32 and FP32-dev at most 4
  * (odd) and 3 (even) workgroups per CU; D3Q19 FP64 even steps with block
- * 64, two cells per thread, at most 2 per CU; everything else uncapped. */
+ * 64, two cells per thread, at most 2 per CU; D3Q27 FP32 and FP32-dev
+ * odd steps at most 3 per CU; everything else uncapped. */
 lbm_status lbm_set_launch(int32_t kernel, int32_t q, int32_t storage, const lbm_launch* cfg);
 lbm_status lbm_get_launch(int32_t kernel, int32_t q, int32_t storage, lbm_launch* cfg);
 

@@ -69,6 +69,10 @@ void launch_defaults() {
         c.max_groups_per_cu = 0;
         if (qi == 0 && (st == LBM_STORE_F32 || st == LBM_STORE_F32DEV))
           c.max_groups_per_cu = k == LBM_KERNEL_ODD ? 4 : (k == LBM_KERNEL_EVEN ? 3 : 0);
+        // D3Q27 FP32 odd step: about 1 % faster at 3 per CU on both the
+        // vessel tree and the packing (its even step depends on geometry)
+        if (qi == 1 && (st == LBM_STORE_F32 || st == LBM_STORE_F32DEV) && k == LBM_KERNEL_ODD)
+          c.max_groups_per_cu = 3;
         if (qi == 0 && st == LBM_STORE_F64 && k == LBM_KERNEL_EVEN) {
           c.block = 64;
           c.cells_per_thread = 2;
