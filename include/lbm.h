@@ -287,7 +287,10 @@ lbm_status lbm_step(lbm_state* state, int32_t n_steps, const lbm_collision* coll
  * on return state->pdf holds the current populations and *spare the other
  * buffer.  The slot layout stays natural, so t must be even on entry and
  * n_steps even (then the state continues seamlessly with lbm_step).  The
- * launch configuration of LBM_KERNEL_ODD is used.  Errors as lbm_step. */
+ * launch configuration of LBM_KERNEL_ODD is used without its residency cap.
+ * The pull kernel reads the int32 index-list (or the compact form with
+ * it): a state whose int32 list was dropped is refused with LBM_EINVAL.
+ * Errors as lbm_step. */
 lbm_status lbm_step_pull(lbm_state* state, void** spare, int32_t n_steps,
                          const lbm_collision* coll, const lbm_bspec* bspec, void* stream);
 
@@ -295,7 +298,9 @@ lbm_status lbm_step_pull(lbm_state* state, void** spare, int32_t n_steps,
  * parity), from the post-collision populations: rho = sum f*,
  * u = (sum c f* - F/2) / rho.
  *  rho  device, stride elements; u device, 3*stride elements (u_x block,
- *       u_y block, u_z block); element type double if out_f64 else float. */
+ *       u_y block, u_z block); element type double if out_f64 else float.
+ * Entries k >= n_fluid are left as they were.  Errors: LBM_EINVAL (state,
+ * collision), LBM_EDEVICE. */
 lbm_status lbm_moments(const lbm_state* state, const lbm_collision* coll, int32_t out_f64,
                        void* rho, void* u, void* stream);
 
@@ -401,10 +406,15 @@ lbm_status lbm_get_launch(int32_t kernel, int32_t q, int32_t storage, lbm_launch
 
 /* Streaming copy dst[0..bytes) = src[0..bytes) with 16-byte vector loads;
  * device pointers, 16-byte aligned, bytes a multiple of 16.  Reference for
- * the achievable HBM bandwidth and for hardware byte counters. */
+ * the achievable HBM bandwidth and for hardware byte counters.
+ * Errors: LBM_EINVAL (alignment, size), LBM_EDEVICE. */
 lbm_status lbm_copy(void* dst, const void* src, uint64_t bytes, void* stream);
 
+/* Message of the last failing call on the calling thread (owned by the
+ * library, valid until that thread's next call; empty when none failed). */
 const char* lbm_last_error(void);
+/* Version of this interface: 4 (launch table with residency caps, unsigned
+ * 32-bit positions, optional int32 index-list next to the run form). */
 int32_t lbm_abi_version(void);
 
 #ifdef __cplusplus
