@@ -327,16 +327,31 @@ lbm_status lbm_reduce(const lbm_state* state, const lbm_collision* coll, void* w
 /* running the state alone with the same launch configuration.           */
 /* ------------------------------------------------------------------ */
 
+/* Device workspace bytes lbm_step_batch needs for n_states states (host
+ * only; 0 for n_states < 1): room for the batch's segment tables (each
+ * state's buffers, sizes and collision parameters, about 160 bytes per state
+ * and parity), which the launches read from device memory.  */
+uint64_t lbm_step_batch_workspace_bytes(int32_t n_states);
+
 /* states[n], colls[n], bspecs[n] (bspecs may be NULL): every state must
- * have the same q, storage and parity (t & 1).  Errors: LBM_ESTATE when
- * they differ, otherwise as lbm_step. */
+ * have the same q, storage and parity (t & 1).  No limit on n.
+ *  workspace        device, >= lbm_step_batch_workspace_bytes(n) bytes
+ *                   (may be NULL when n == 1).  The call writes the
+ *                   segment tables into it on `stream` (kernels, no host
+ *                   copies) before the first step; it must not be reused
+ *                   by another call on another stream until this call's
+ *                   launches have run.
+ *  workspace_bytes  its size.
+ * Errors: LBM_ESTATE when the states differ, LBM_ENOMEM when the workspace
+ * is too small, otherwise as lbm_step. */
 lbm_status lbm_step_batch(lbm_state* const* states, const lbm_collision* const* colls,
                           const lbm_bspec* const* bspecs, int32_t n_states, int32_t n_steps,
-                          void* stream);
+                          void* workspace, uint64_t workspace_bytes, void* stream);
 
-/* Per-state reductions of lbm_reduce for n states at once, bitwise equal
- * to calling lbm_reduce on each.  workspace >= sum of
- * lbm_reduce_workspace_bytes over the states.  host_out[n].  SYNC. */
+/* Per-state reductions of lbm_reduce for n states at once (no limit on n),
+ * bitwise equal to calling lbm_reduce on each.  workspace >= sum of
+ * lbm_reduce_workspace_bytes over the states (it also holds the batch's
+ * segment table).  host_out[n].  SYNC. */
 lbm_status lbm_reduce_batch(const lbm_state* const* states, const lbm_collision* const* colls,
                             int32_t n_states, void* workspace, lbm_reduction* host_out,
                             void* stream);
@@ -413,8 +428,9 @@ lbm_status lbm_copy(void* dst, const void* src, uint64_t bytes, void* stream);
 /* Message of the last failing call on the calling thread (owned by the
  * library, valid until that thread's next call; empty when none failed). */
 const char* lbm_last_error(void);
-/* Version of this interface: 4 (launch table with residency caps, unsigned
- * 32-bit positions, optional int32 index-list next to the run form). */
+/* Version of this interface: 5 (launch table with residency caps, unsigned
+ * 32-bit positions, optional int32 index-list next to the run form, batch
+ * segment tables in a caller workspace). */
 int32_t lbm_abi_version(void);
 
 #ifdef __cplusplus

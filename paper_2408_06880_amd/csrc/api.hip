@@ -8,6 +8,7 @@
 
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/lbm.h"
 #include "internal.hpp"
@@ -301,7 +302,7 @@ uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); 
 
 extern "C" {
 
-int32_t lbm_abi_version(void) { return 4; }
+int32_t lbm_abi_version(void) { return 5; }
 
 const char* lbm_last_error(void) { return g_err.c_str(); }
 
@@ -528,50 +529,92 @@ lbm_status lbm_init_equilibrium(lbm_state* s, double rho0, const double* u0, voi
   return LBM_OK;
 }
 
+// One launch group of a step: the segments [first, first + nseg) of the
+// call's segment list, all read through one kernel (index form, mode).
+struct LaunchGroup {
+  int mode, form;
+  uint32_t first, nseg, ntiles;
+};
+
+static uint64_t seg_table_bytes(int64_t n) { return align256((uint64_t)n * sizeof(Seg)); }
+
+// Advance n states by n_steps AA steps.  The segment lists of both parities
+// are planned once per call; when a launch covers several states their table
+// is written once into `table` (device, room for 2n segments) before the
+// first step.
 static lbm_status step_group(lbm_state* const* states, const lbm_collision* const* colls,
                              const lbm_bspec* const* bspecs, int32_t n, int32_t n_steps,
-                             hipStream_t st) {
+                             Seg* table, hipStream_t st) {
   const int q = states[0]->layout.q, storage = states[0]->storage;
   const int kind = colls[0]->kind;
+  if (n_steps == 0) return LBM_OK;
+  const lbm_launch cfg_odd = get_cfg(LBM_KERNEL_ODD, q, storage);
+  lbm_launch cfg_even = get_cfg(LBM_KERNEL_EVEN, q, storage);
+  // Two cells per thread need an even stride: the 2-wide accesses stay
+  // aligned and the second cell of the last pair is a padding slot.
+  bool even_strides = true;
+  for (int32_t j = 0; j < n; ++j) even_strides = even_strides && (states[j]->layout.stride % 2 == 0);
+  const uint32_t cpt = (cfg_even.cells_per_thread == 2 && even_strides) ? 2 : 1;
+  // a residency cap chosen for the two-cell kernel does not carry over to
+  // its one-cell fallback
+  if (cfg_even.cells_per_thread == 2 && cpt == 1) cfg_even.max_groups_per_cu = 0;
+
+  std::vector<Seg> segs;
+  segs.reserve(2 * (size_t)n);
+  std::vector<LaunchGroup> odd_groups, even_groups;
+  // Odd steps run one launch per index form, each form being a kernel of
+  // its own; even steps never read indices.
+  for (int form = IDX_I32; form <= IDX_RUN; ++form) {
+    LaunchGroup gr{form == IDX_16 && cfg_odd.pipelined == 1 ? MODE_ODD_PIPE : MODE_ODD, form,
+                   (uint32_t)segs.size(), 0, 0};
+    for (int32_t j = 0; j < n; ++j) {
+      if (states[j]->layout.n_fluid == 0 || index_form(states[j]) != form) continue;
+      Seg g = make_seg(states[j], colls[j]);
+      g.tile0 = gr.ntiles;
+      gr.ntiles += ceil_div(g.nf, (uint64_t)cfg_odd.block);
+      segs.push_back(g);
+      gr.nseg += 1;
+    }
+    if (gr.nseg > 0) odd_groups.push_back(gr);
+  }
+  {
+    LaunchGroup gr{cpt == 2 ? MODE_EVEN2 : MODE_EVEN, IDX_I32, (uint32_t)segs.size(), 0, 0};
+    for (int32_t j = 0; j < n; ++j) {
+      if (states[j]->layout.n_fluid == 0) continue;
+      Seg g = make_seg(states[j], colls[j]);
+      g.tile0 = gr.ntiles;
+      gr.ntiles += ceil_div(g.nf, (uint64_t)cfg_even.block * cpt);
+      segs.push_back(g);
+      gr.nseg += 1;
+    }
+    if (gr.nseg > 0) even_groups.push_back(gr);
+  }
+  bool need_table = false;
+  for (const auto& gr : odd_groups) need_table = need_table || gr.nseg > 1;
+  for (const auto& gr : even_groups) need_table = need_table || gr.nseg > 1;
+  if (need_table) {
+    if (!table) return fail(LBM_EINVAL, "a batch of several solves needs a workspace");
+    HIP_TRY(launch_put_segs(segs.data(), (uint32_t)segs.size(), table, st), "segment table");
+  }
+
   for (int32_t step = 0; step < n_steps; ++step) {
     const bool odd = (states[0]->t & 1) == 0;
-    lbm_launch cfg = get_cfg(odd ? LBM_KERNEL_ODD : LBM_KERNEL_EVEN, q, storage);
+    const lbm_launch& cfg = odd ? cfg_odd : cfg_even;
     for (int32_t j = 0; j < n; ++j) {
       lbm_status rc = link_update(states[j], bspecs ? bspecs[j] : nullptr, st);
       if (rc) return rc;
     }
-    // Odd steps run one launch (group) per index form, each form being a
-    // kernel of its own; even steps never read indices.
-    // Two cells per thread need an even stride: the 2-wide accesses stay
-    // aligned and the second cell of the last pair is a padding slot.
-    bool even_strides = true;
-    for (int32_t j = 0; j < n; ++j) even_strides = even_strides && (states[j]->layout.stride % 2 == 0);
-    const uint32_t cpt = (!odd && cfg.cells_per_thread == 2 && even_strides) ? 2 : 1;
-    // a residency cap chosen for the two-cell kernel does not carry over to
-    // its one-cell fallback
-    if (!odd && cfg.cells_per_thread == 2 && cpt == 1) cfg.max_groups_per_cu = 0;
-    for (int form = IDX_I32; form <= IDX_RUN; ++form) {
-      int32_t j = 0;
-      while (j < n) {
-        StepArgs a;
-        memset(&a, 0, sizeof(a));
-        a.xcd_remap = cfg.xcd_remap;
-        uint32_t tiles = 0;
-        int ns = 0;
-        for (; j < n && ns < kMaxSeg; ++j) {
-          const int fj = odd ? index_form(states[j]) : IDX_I32;
-          if (states[j]->layout.n_fluid == 0 || fj != form) continue;
-          Seg g = make_seg(states[j], colls[j]);
-          g.tile0 = tiles;
-          tiles += ceil_div(g.nf, (uint64_t)cfg.block * cpt);
-          a.seg[ns++] = g;
-        }
-        a.nseg = ns;
-        a.ntiles = tiles;
-        const int mode = !odd ? (cpt == 2 ? 4 : 0) : (form == IDX_16 && cfg.pipelined == 1 ? 3 : 1);
-        if (ns > 0) HIP_TRY(launch_aa(q, kind, storage, mode, form, a, cfg, st), "AA step");
-      }
-      if (!odd) break;
+    for (const LaunchGroup& gr : odd ? odd_groups : even_groups) {
+      StepArgs a;
+      memset(&a, 0, sizeof(a));
+      a.xcd_remap = cfg.xcd_remap;
+      a.nseg = (int32_t)gr.nseg;
+      a.ntiles = gr.ntiles;
+      if (gr.nseg == 1)
+        a.seg0 = segs[gr.first];
+      else
+        a.segs = table + gr.first;
+      HIP_TRY(launch_aa(q, kind, storage, gr.mode, gr.form, a, cfg, st), "AA step");
     }
     for (int32_t j = 0; j < n; ++j) states[j]->t += 1;
   }
@@ -588,7 +631,7 @@ lbm_status lbm_step(lbm_state* s, int32_t n_steps, const lbm_collision* c, const
   lbm_state* arr[1] = {s};
   const lbm_collision* carr[1] = {c};
   const lbm_bspec* barr[1] = {bs};
-  return step_group(arr, carr, barr, 1, n_steps, (hipStream_t)stream);
+  return step_group(arr, carr, barr, 1, n_steps, nullptr, (hipStream_t)stream);
 }
 
 lbm_status lbm_step_pull(lbm_state* s, void** spare, int32_t n_steps, const lbm_collision* c,
@@ -620,10 +663,10 @@ lbm_status lbm_step_pull(lbm_state* s, void** spare, int32_t n_steps, const lbm_
       Seg g = make_seg(s, c);
       g.dst = *spare;
       g.tile0 = 0;
-      a.seg[0] = g;
+      a.seg0 = g;
       a.nseg = 1;
       a.ntiles = ceil_div(g.nf, (uint64_t)cfg.block);
-      HIP_TRY(launch_aa(s->layout.q, c->kind, s->storage, 2, idx, a, cfg, st),
+      HIP_TRY(launch_aa(s->layout.q, c->kind, s->storage, MODE_PULL, idx, a, cfg, st),
               "pull step");
       void* tmp = s->pdf;
       s->pdf = *spare;
@@ -634,9 +677,14 @@ lbm_status lbm_step_pull(lbm_state* s, void** spare, int32_t n_steps, const lbm_
   return LBM_OK;
 }
 
+uint64_t lbm_step_batch_workspace_bytes(int32_t n_states) {
+  if (n_states < 1) return 0;
+  return 2 * seg_table_bytes(n_states);
+}
+
 lbm_status lbm_step_batch(lbm_state* const* states, const lbm_collision* const* colls,
                           const lbm_bspec* const* bspecs, int32_t n, int32_t n_steps,
-                          void* stream) {
+                          void* workspace, uint64_t workspace_bytes, void* stream) {
   if (!states || !colls || n < 1) return fail(LBM_EINVAL, "lbm_step_batch: empty batch");
   if (n_steps < 0) return fail(LBM_EINVAL, "n_steps must be >= 0");
   for (int32_t j = 0; j < n; ++j) {
@@ -648,7 +696,14 @@ lbm_status lbm_step_batch(lbm_state* const* states, const lbm_collision* const* 
         ((states[j]->t ^ states[0]->t) & 1) || colls[j]->kind != colls[0]->kind)
       return fail(LBM_ESTATE, "batch member %d differs in q, storage, parity or collision kind", j);
   }
-  return step_group(states, colls, bspecs, n, n_steps, (hipStream_t)stream);
+  if (n > 1) {
+    if (!workspace) return fail(LBM_EINVAL, "workspace is NULL");
+    if (workspace_bytes < lbm_step_batch_workspace_bytes(n))
+      return fail(LBM_ENOMEM, "workspace of %llu bytes is below the %llu bytes %d states need",
+                  (unsigned long long)workspace_bytes,
+                  (unsigned long long)lbm_step_batch_workspace_bytes(n), n);
+  }
+  return step_group(states, colls, bspecs, n, n_steps, (Seg*)workspace, (hipStream_t)stream);
 }
 
 lbm_status lbm_moments(const lbm_state* s, const lbm_collision* c, int32_t out_f64, void* rho,
@@ -667,13 +722,80 @@ lbm_status lbm_moments(const lbm_state* s, const lbm_collision* c, int32_t out_f
 
 uint64_t lbm_reduce_workspace_bytes(const lbm_layout* L) {
   if (!L || L->n_fluid < 0) return 0;
-  return align256((uint64_t)ceil_div((uint64_t)L->n_fluid, kRedBlock) * 5 * sizeof(double)) + 256;
+  // tile partials; 8 result doubles; this state's entry of a batch's
+  // segment table
+  return align256((uint64_t)ceil_div((uint64_t)L->n_fluid, kRedBlock) * 5 * sizeof(double)) + 256 +
+         seg_table_bytes(1);
 }
 
-lbm_status lbm_reduce_batch(const lbm_state* const* states, const lbm_collision* const* colls,
-                            int32_t n, void* workspace, lbm_reduction* out, void* stream) {
+// Scratch bytes the reductions of n states need: tile partials, 8 result
+// doubles per state and (n > 1) the segment table.
+static uint64_t reduce_scratch_bytes(const lbm_state* const* states, int32_t n) {
+  uint64_t tiles = 0;
+  for (int32_t j = 0; j < n; ++j) tiles += ceil_div((uint64_t)states[j]->layout.n_fluid, kRedBlock);
+  return align256(tiles * 5 * sizeof(double)) + align256((uint64_t)n * 8 * sizeof(double)) +
+         (n > 1 ? seg_table_bytes(n) : 0);
+}
+
+// Reductions of n states into `ws` (laid out as reduce_scratch_bytes says);
+// segs[n] and host[8n] are host buffers of the caller.  Fills out[n]; SYNC.
+static lbm_status reduce_states(const lbm_state* const* states, const lbm_collision* const* colls,
+                                int32_t n, char* ws, uint64_t ws_bytes, Seg* segs, double* host,
+                                lbm_reduction* out, hipStream_t st) {
+  const int q = states[0]->layout.q, storage = states[0]->storage;
+  const bool odd_t = (states[0]->t & 1) != 0;
+  const uint64_t need = reduce_scratch_bytes(states, n);
+  if (need > ws_bytes)
+    return fail(LBM_ENOMEM, "reduction of %d state(s) needs %llu bytes of scratch (%llu available)",
+                n, (unsigned long long)need, (unsigned long long)ws_bytes);
+  uint32_t tiles = 0;
+  for (int32_t j = 0; j < n; ++j) {
+    segs[j] = make_seg(states[j], colls[j]);
+    segs[j].tile0 = tiles;
+    tiles += ceil_div(segs[j].nf, kRedBlock);
+  }
+  const uint64_t part_b = align256((uint64_t)tiles * 5 * sizeof(double));
+  const uint64_t out_b = align256((uint64_t)n * 8 * sizeof(double));
+  double* partials = (double*)ws;
+  double* dout = (double*)(ws + part_b);
+  StepArgs a;
+  memset(&a, 0, sizeof(a));
+  a.nseg = n;
+  a.ntiles = tiles;
+  if (n == 1) {
+    a.seg0 = segs[0];
+  } else {
+    Seg* table = (Seg*)(ws + part_b + out_b);
+    HIP_TRY(launch_put_segs(segs, (uint32_t)n, table, st), "segment table");
+    a.segs = table;
+  }
+  HIP_TRY(launch_reduce(q, storage, a, odd_t, partials, dout, st), "reduce");
+  HIP_TRY(hipMemcpyAsync(host, dout, sizeof(double) * 8 * n, hipMemcpyDeviceToHost, st),
+          "reduce copy");
+  HIP_TRY(hipStreamSynchronize(st), "reduce sync");
+  bool finite_all = true;
+  for (int j = 0; j < n; ++j) {
+    lbm_reduction& r = out[j];
+    r.mass = host[j * 8 + 0];
+    r.mom[0] = host[j * 8 + 2];
+    r.mom[1] = host[j * 8 + 3];
+    r.mom[2] = host[j * 8 + 4];
+    r.n_fluid = (int64_t)host[j * 8 + 6];
+    r.finite = (host[j * 8 + 5] == 0.0 && isfinite(r.mass) && isfinite(r.mom[0]) &&
+                isfinite(r.mom[1]) && isfinite(r.mom[2]))
+                   ? 1
+                   : 0;
+    r.reserved = 0;
+    finite_all = finite_all && r.finite;
+  }
+  if (!finite_all) return fail(LBM_EUNSTABLE, "non-finite values in the reduction");
+  return LBM_OK;
+}
+
+static lbm_status check_reduce_batch(const lbm_state* const* states,
+                                     const lbm_collision* const* colls, int32_t n,
+                                     lbm_reduction* out) {
   if (!states || !colls || n < 1 || !out) return fail(LBM_EINVAL, "lbm_reduce_batch: bad arguments");
-  if (!workspace) return fail(LBM_EINVAL, "workspace is NULL");
   for (int32_t j = 0; j < n; ++j) {
     lbm_status rc = check_state(states[j]);
     if (rc) return rc;
@@ -683,51 +805,21 @@ lbm_status lbm_reduce_batch(const lbm_state* const* states, const lbm_collision*
         ((states[j]->t ^ states[0]->t) & 1))
       return fail(LBM_ESTATE, "batch member %d differs in q, storage or parity", j);
   }
-  hipStream_t st = (hipStream_t)stream;
-  const int q = states[0]->layout.q, storage = states[0]->storage;
-  const bool odd_t = (states[0]->t & 1) != 0;
-  char* ws = (char*)workspace;
-  bool finite_all = true;
-  for (int32_t j0 = 0; j0 < n; j0 += kMaxSeg) {
-    StepArgs a;
-    memset(&a, 0, sizeof(a));
-    uint32_t tiles = 0;
-    int ns = 0;
-    uint64_t bytes = 0;
-    for (int32_t j = j0; j < n && j < j0 + kMaxSeg; ++j) {
-      Seg g = make_seg(states[j], colls[j]);
-      g.tile0 = tiles;
-      tiles += ceil_div(g.nf, kRedBlock);
-      a.seg[ns++] = g;
-      bytes += lbm_reduce_workspace_bytes(&states[j]->layout);
-    }
-    a.nseg = ns;
-    a.ntiles = tiles;
-    double* partials = (double*)ws;
-    double* dout = (double*)(ws + align256((uint64_t)tiles * 5 * sizeof(double)));
-    HIP_TRY(launch_reduce(q, storage, a, odd_t, partials, dout, st), "reduce");
-    double host[kMaxSeg * 8];
-    HIP_TRY(hipMemcpyAsync(host, dout, sizeof(double) * 8 * ns, hipMemcpyDeviceToHost, st),
-            "reduce copy");
-    HIP_TRY(hipStreamSynchronize(st), "reduce sync");
-    for (int j = 0; j < ns; ++j) {
-      lbm_reduction& r = out[j0 + j];
-      r.mass = host[j * 8 + 0];
-      r.mom[0] = host[j * 8 + 2];
-      r.mom[1] = host[j * 8 + 3];
-      r.mom[2] = host[j * 8 + 4];
-      r.n_fluid = (int64_t)host[j * 8 + 6];
-      r.finite = (host[j * 8 + 5] == 0.0 && isfinite(r.mass) && isfinite(r.mom[0]) &&
-                  isfinite(r.mom[1]) && isfinite(r.mom[2]))
-                     ? 1
-                     : 0;
-      r.reserved = 0;
-      finite_all = finite_all && r.finite;
-    }
-    ws += bytes;
-  }
-  if (!finite_all) return fail(LBM_EUNSTABLE, "non-finite values in the reduction");
   return LBM_OK;
+}
+
+lbm_status lbm_reduce_batch(const lbm_state* const* states, const lbm_collision* const* colls,
+                            int32_t n, void* workspace, lbm_reduction* out, void* stream) {
+  lbm_status rc = check_reduce_batch(states, colls, n, out);
+  if (rc) return rc;
+  if (!workspace) return fail(LBM_EINVAL, "workspace is NULL");
+  // the caller provides the sum of the states' workspace sizes
+  uint64_t bytes = 0;
+  for (int32_t j = 0; j < n; ++j) bytes += lbm_reduce_workspace_bytes(&states[j]->layout);
+  std::vector<Seg> segs((size_t)n);
+  std::vector<double> host((size_t)n * 8);
+  return reduce_states(states, colls, n, (char*)workspace, bytes, segs.data(), host.data(), out,
+                       (hipStream_t)stream);
 }
 
 lbm_status lbm_reduce(const lbm_state* s, const lbm_collision* c, void* workspace,

@@ -1,5 +1,7 @@
 // Equilibrium initialisation, boundary-link updates, per-cell moments,
 // deterministic FP64 reductions and the streaming copy kernel.
+#include <string.h>
+
 #include "collide.hpp"
 #include "internal.hpp"
 
@@ -255,7 +257,7 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce_tiles(const StepArgs a, do
   __shared__ double sh[kRedBlock / 64][5];
   const uint32_t tile = blockIdx.x;
   const int s = seg_of(a, tile);
-  const Seg& g = a.seg[s];
+  const Seg& g = seg_at(a, s);
   const uint32_t k = (tile - g.tile0) * kRedBlock + threadIdx.x;
   double v[5] = {0, 0, 0, 0, 0};
   if (k < g.nf) {
@@ -295,8 +297,8 @@ __global__ __launch_bounds__(256) void k_reduce_segs(const StepArgs a, const dou
                                                      double* out) {
   __shared__ double sh[256][5];
   const int s = blockIdx.x;
-  const uint32_t t0 = a.seg[s].tile0;
-  const uint32_t t1 = (s + 1 < a.nseg) ? a.seg[s + 1].tile0 : a.ntiles;
+  const uint32_t t0 = seg_at(a, s).tile0;
+  const uint32_t t1 = (s + 1 < a.nseg) ? seg_at(a, s + 1).tile0 : a.ntiles;
   double v[5] = {0, 0, 0, 0, 0};
   for (uint32_t t = t0 + threadIdx.x; t < t1; t += 256)
     for (int m = 0; m < 5; ++m) v[m] += partials[(size_t)t * 5 + m];
@@ -308,7 +310,7 @@ __global__ __launch_bounds__(256) void k_reduce_segs(const StepArgs a, const dou
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const double nf = (double)a.seg[s].nf;
+    const double nf = (double)seg_at(a, s).nf;
     out[s * 8 + 0] = nf + sh[0][0];  // mass
     out[s * 8 + 1] = sh[0][0];       // sum of density deviations
     out[s * 8 + 2] = sh[0][1];
@@ -352,6 +354,38 @@ hipError_t launch_reduce(int q, int storage, const StepArgs& a, bool odd_t, doub
   if (q == 19) return launch_reduce_q<19>(storage, a, odd_t, partials, out, st);
   if (q == 27) return launch_reduce_q<27>(storage, a, odd_t, partials, out, st);
   return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------ segment tables
+// A batch launch reads its segment table from device memory.  The host
+// writes it with this kernel (up to kSegChunk entries per launch, from the
+// kernel arguments) instead of a host-to-device copy, so the table travels
+// in stream order, needs no pinned host buffer and can be captured.
+struct SegChunk {
+  uint32_t n;
+  uint32_t pad;
+  Seg seg[kSegChunk];
+};
+
+__global__ __launch_bounds__(256) void k_put_segs(const SegChunk c, Seg* dst) {
+  static_assert(sizeof(Seg) % 8 == 0, "segments are copied as 8-byte words");
+  const uint32_t words = c.n * (uint32_t)(sizeof(Seg) / 8);
+  const uint64_t* src = reinterpret_cast<const uint64_t*>(c.seg);
+  uint64_t* out = reinterpret_cast<uint64_t*>(dst);
+  for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) out[w] = src[w];
+}
+
+hipError_t launch_put_segs(const Seg* host, uint32_t n, Seg* dev, hipStream_t st) {
+  for (uint32_t j = 0; j < n; j += kSegChunk) {
+    SegChunk c;
+    memset(&c, 0, sizeof(c));
+    c.n = n - j < kSegChunk ? n - j : kSegChunk;
+    memcpy(c.seg, host + j, c.n * sizeof(Seg));
+    hipLaunchKernelGGL(k_put_segs, dim3(1), dim3(256), 0, st, c, dev + j);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // -------------------------------------------------------------- copy

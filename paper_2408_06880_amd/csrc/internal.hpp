@@ -43,6 +43,10 @@ constexpr int kRedBlock = 256;
 hipError_t launch_reduce(int q, int storage, const StepArgs& a, bool odd_t, double* partials,
                          double* out, hipStream_t st);
 hipError_t launch_copy(void* dst, const void* src, uint64_t bytes, hipStream_t st);
+// Write n segments from host memory into the device table `dev` (stream
+// ordered; kernel launches carrying at most kSegChunk segments each).
+constexpr uint32_t kSegChunk = 16;
+hipError_t launch_put_segs(const Seg* host, uint32_t n, Seg* dev, hipStream_t st);
 // Storage conversion of a whole PDF-list (q * S slots), format sa -> sb.
 hipError_t launch_convert(int q, int sa, int sb, const void* src, void* dst, uint32_t S,
                           float inv_scale_a, float scale_b, hipStream_t st);

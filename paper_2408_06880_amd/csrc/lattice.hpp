@@ -105,17 +105,22 @@ struct Store<ST_BF16DEV> {
 };
 
 // ---------------------------------------------------------------------------
-// Launch arguments.  One launch advances up to kMaxSeg independent solves
-// ("segments"); segment s owns workgroup tiles [tile0_s, tile0_{s+1}).  The
-// table travels in the kernel arguments (64 segments: about 10 KB).
+// Launch arguments.  One launch advances one or more independent solves
+// ("segments"); segment s owns workgroup tiles [tile0_s, tile0_{s+1}).  A
+// single segment travels in the kernel arguments; a batch of several reads
+// its table from device memory (a caller workspace written by a small
+// kernel before the launches), so a launch carries a pointer, not the table.
 // ---------------------------------------------------------------------------
-constexpr int kMaxSeg = 64;
 
 // Compact index-list: tiles of kTile16 list positions.
 constexpr uint32_t kTile16 = 256;
 constexpr uint16_t kBounce16 = 0xFFFFu;  // upstream cell not fluid
 constexpr uint16_t kEscape16 = 0xFFFEu;  // read the int32 index-list
 constexpr uint32_t kMaxOff16 = 0xFFFDu;  // largest stored offset
+
+// Step kernels: even, odd, two-array pull, pipelined odd (compact
+// index-list), even with two cells per thread.
+enum StepMode { MODE_EVEN = 0, MODE_ODD = 1, MODE_PULL = 2, MODE_ODD_PIPE = 3, MODE_EVEN2 = 4 };
 
 // Index-list forms read by the odd step.
 enum IndexForm { IDX_I32 = 0, IDX_16 = 1, IDX_RUN = 2 };
@@ -148,8 +153,14 @@ struct StepArgs {
   uint32_t ntiles;
   int32_t xcd_remap;
   int32_t pad;
-  Seg seg[kMaxSeg];
+  const Seg* segs;         // device table of nseg segments when nseg > 1
+  Seg seg0;                // the segment when nseg == 1
 };
+
+// Segment s of a launch.
+__device__ __forceinline__ const Seg& seg_at(const StepArgs& a, int s) {
+  return a.nseg == 1 ? a.seg0 : a.segs[s];
+}
 
 // Pull position of population i of cell k from the compact index-list
 // (t16 = the cell's compact tile; tile bases are stored [tile][direction]).
@@ -175,10 +186,11 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t v, uint32_t n) {
 // Segment of a tile: the last segment whose first tile is not after it
 // (binary search; first tiles do not decrease with the segment number).
 __device__ __forceinline__ int seg_of(const StepArgs& a, uint32_t tile) {
+  if (a.nseg == 1) return 0;
   int lo = 0, hi = a.nseg - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (a.seg[mid].tile0 <= tile)
+    if (a.segs[mid].tile0 <= tile)
       lo = mid;
     else
       hi = mid - 1;

@@ -113,8 +113,6 @@ __device__ __forceinline__ void run_positions(const Seg& g, uint32_t k, uint32_t
   }
 }
 
-enum StepMode { MODE_EVEN = 0, MODE_ODD = 1, MODE_PULL = 2, MODE_ODD_PIPE = 3, MODE_EVEN2 = 4 };
-
 template <int Q, int COLL, int ST, int MODE, int IDX>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU))) void k_aa_step(const StepArgs a) {
@@ -124,7 +122,7 @@ __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU))) void k_aa_step(const
   using R = typename SP::R;
   const uint32_t tile = a.xcd_remap ? xcd_tile(blockIdx.x, a.ntiles) : blockIdx.x;
   const int s = seg_of(a, tile);
-  const Seg g = a.seg[s];
+  const Seg g = seg_at(a, s);
   const uint32_t k = (tile - g.tile0) * blockDim.x + threadIdx.x;
   if (k >= g.nf) return;
   T* __restrict__ pdf = static_cast<T*>(g.pdf);
@@ -214,7 +212,7 @@ __global__ __launch_bounds__(256) void k_even_pair(const StepArgs a) {
   typedef T T2 __attribute__((ext_vector_type(2)));
   const uint32_t tile = a.xcd_remap ? xcd_tile(blockIdx.x, a.ntiles) : blockIdx.x;
   const int s = seg_of(a, tile);
-  const Seg g = a.seg[s];
+  const Seg g = seg_at(a, s);
   const uint32_t k = 2 * ((tile - g.tile0) * blockDim.x + threadIdx.x);
   if (k >= g.nf) return;
   T* __restrict__ pdf = static_cast<T*>(g.pdf);
@@ -267,7 +265,7 @@ __global__ __launch_bounds__(256) void k_odd_pipe(const StepArgs a) {
   int s = seg_of(a, tile);
   uint32_t o[Q];
   {
-    const Seg g = a.seg[s];
+    const Seg g = seg_at(a, s);
     pipe_load_offsets<Q>(g, (tile - g.tile0) * blockDim.x + threadIdx.x, o);
   }
   while (true) {
@@ -279,11 +277,11 @@ __global__ __launch_bounds__(256) void k_odd_pipe(const StepArgs a) {
     if (has_next) {
       tn = a.xcd_remap ? xcd_tile(vn, a.ntiles) : vn;
       sn = seg_of(a, tn);
-      const Seg gn = a.seg[sn];
+      const Seg gn = seg_at(a, sn);
       pipe_load_offsets<Q>(gn, (tn - gn.tile0) * blockDim.x + threadIdx.x, on);
     }
     {
-      const Seg g = a.seg[s];
+      const Seg g = seg_at(a, s);
       const uint32_t k = (tile - g.tile0) * blockDim.x + threadIdx.x;
       if (k < g.nf) {
         T* __restrict__ pdf = static_cast<T*>(g.pdf);

@@ -300,6 +300,35 @@ def vessel_tree(n=512, r0=24.0, ratio=0.79, k_len=6.0, seed=7, angle_deg=(20.0, 
     return mask, 0, info
 
 
+def hybrid_bed(L=256, phi_bed=0.4, r_min=4.0, r_max=12.0, seed=15, batch=16):
+    """Particle bed under free flow (the scenario that motivates a block-wise
+    choice between sparse and dense storage): a periodic box of edge L whose
+    lower half (z < L/2) holds overlapping spheres (centres uniform in that
+    half, radii uniform in [r_min, r_max]) added in batches until the lower
+    half's porosity is <= phi_bed, and whose upper half is fluid (spheres
+    reaching into it are cut off there).  Returns (labels, periodic, info)."""
+    rng = np.random.default_rng(seed)
+    mask = np.zeros((L, L, L), np.uint8)
+    half = L // 2
+    lower = half * L * L
+    n = 0
+    while True:
+        solid = int(np.count_nonzero(mask[:half]))
+        if (lower - solid) / lower <= phi_bed:
+            break
+        for _ in range(batch):
+            c = np.array([rng.uniform(0.0, L), rng.uniform(0.0, L), rng.uniform(0.0, half)])
+            _stamp(mask, c, rng.uniform(r_min, r_max))
+            n += 1
+    mask[half:] = 0
+    nf = int(np.count_nonzero(mask == 0))
+    info = {"kind": "hybrid_bed", "L": L, "phi_bed_target": phi_bed,
+            "phi_bed": 1.0 - np.count_nonzero(mask[:half]) / lower, "phi": nf / L ** 3,
+            "n_fluid": nf, "n_fluid_free": L * L * (L - half), "seed": seed, "n_spheres": n,
+            "r": [r_min, r_max]}
+    return mask, PERIODIC_ALL, info
+
+
 def workload_c0():
     """32^3 periodic box, non-overlapping spheres r in [3, 5], porosity ~0.6, seed 1."""
     lab, info = rsa_spheres(32, 3.0, 5.0, 0.6, seed=1)

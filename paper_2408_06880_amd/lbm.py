@@ -117,9 +117,11 @@ _SIGS = {
     "lbm_reduce_workspace_bytes": (_u64, [ctypes.POINTER(lbm_layout)]),
     "lbm_reduce": (_i32, [ctypes.POINTER(lbm_state), ctypes.POINTER(lbm_collision), _vp,
                           ctypes.POINTER(lbm_reduction), _vp]),
+    "lbm_step_batch_workspace_bytes": (_u64, [_i32]),
     "lbm_step_batch": (_i32, [ctypes.POINTER(ctypes.POINTER(lbm_state)),
                               ctypes.POINTER(ctypes.POINTER(lbm_collision)),
-                              ctypes.POINTER(ctypes.POINTER(lbm_bspec)), _i32, _i32, _vp]),
+                              ctypes.POINTER(ctypes.POINTER(lbm_bspec)), _i32, _i32, _vp, _u64,
+                              _vp]),
     "lbm_reduce_batch": (_i32, [ctypes.POINTER(ctypes.POINTER(lbm_state)),
                                 ctypes.POINTER(ctypes.POINTER(lbm_collision)), _i32, _vp,
                                 ctypes.POINTER(lbm_reduction), _vp]),
@@ -275,7 +277,16 @@ def lbm_reduce(state, coll, workspace, stream=None, check=True):
     return out
 
 
-def lbm_step_batch(states, colls, bspecs, n_steps, stream=None):
+def lbm_step_batch_workspace_bytes(n_states):
+    return int(load().lbm_step_batch_workspace_bytes(int(n_states)))
+
+
+def lbm_step_batch(states, colls, bspecs, n_steps, stream=None, workspace=None,
+                   workspace_bytes=None):
+    """workspace: device tensor of at least lbm_step_batch_workspace_bytes(n)
+    bytes (or a raw device address with workspace_bytes); None allocates one
+    for this call (its memory is kept from reuse until the call's launches on
+    `stream` have run)."""
     n = len(states)
     sp = (ctypes.POINTER(lbm_state) * n)(*[ctypes.pointer(s) for s in states])
     cp = (ctypes.POINTER(lbm_collision) * n)(*[ctypes.pointer(c) for c in colls])
@@ -283,7 +294,22 @@ def lbm_step_batch(states, colls, bspecs, n_steps, stream=None):
     if bspecs is not None:
         bp = (ctypes.POINTER(lbm_bspec) * n)(
             *[ctypes.pointer(b) if b is not None else ctypes.POINTER(lbm_bspec)() for b in bspecs])
-    _call("lbm_step_batch", sp, cp, bp, n, int(n_steps), _stream(stream))
+    need = lbm_step_batch_workspace_bytes(n)
+    if workspace is None and n > 1:
+        import torch
+        workspace = torch.empty(need, dtype=torch.uint8, device="cuda")
+        st = stream if stream is not None else torch.cuda.current_stream()
+        if isinstance(st, int):
+            st = torch.cuda.ExternalStream(st)
+        workspace.record_stream(st)
+    if workspace_bytes is not None:
+        nbytes = int(workspace_bytes)
+    elif workspace is not None and not isinstance(workspace, int):
+        nbytes = workspace.numel() * workspace.element_size()
+    else:
+        nbytes = 0
+    _call("lbm_step_batch", sp, cp, bp, n, int(n_steps), _ptr(workspace), nbytes,
+          _stream(stream))
 
 
 def lbm_reduce_batch(states, colls, workspace, stream=None, check=True):

@@ -358,6 +358,9 @@ class GpuStepper:
         import torch
         self.torch = torch
         self._ws = None
+        self._step_ws = None
+        # the stream every step, reduction and conversion runs on
+        self._step_stream = stream if stream is not None else torch.cuda.current_stream()
         # builds run on a stream of their own so they overlap the steps
         self._build_stream = torch.cuda.Stream()
         # Geometry generation runs on host threads while the GPU steps the
@@ -431,6 +434,13 @@ class GpuStepper:
             sol = self.lbm.Solver(dom, self.storage, self.dev_exp)
             sol.init(stream=bs)
         bs.synchronize()
+        # The buffers come from the build stream's pool but are used on the
+        # step stream from now on: when one is released (retirement, or the
+        # old PDF-list after a refinement), the allocator must not hand it to
+        # a later build before the step stream's queued work has read it.
+        for t in (dom.cells, dom.index, dom.links, dom.index16, dom.runs, sol.pdf, sol._red_ws):
+            if t is not None:
+                t.record_stream(self._step_stream)
         coll = self.lbm.collision(self.lbm.COLL_TRT, tau=r.tau, magic=self.magic,
                                   force=(r.force, 0.0, 0.0))
         return {"req": r, "sol": sol, "coll": coll}
@@ -445,10 +455,16 @@ class GpuStepper:
         return groups.values()
 
     def step(self, hs, n):
-        # one batch per storage format (refined solves run in finer storage)
+        # one batch per storage format (refined solves run in finer storage);
+        # the segment-table workspace is reused in stream order
+        need = self.lbm.lbm_step_batch_workspace_bytes(len(hs))
+        if self._step_ws is None or self._step_ws.numel() < need:
+            self._step_ws = self.torch.empty(max(need, 1 << 16), dtype=self.torch.uint8,
+                                             device="cuda")
         for idx in self._by_storage(hs):
             self.lbm.lbm_step_batch([hs[j]["sol"].state for j in idx],
-                                    [hs[j]["coll"] for j in idx], None, n, self.stream)
+                                    [hs[j]["coll"] for j in idx], None, n, self.stream,
+                                    workspace=self._step_ws)
 
     def reduce(self, hs):
         need = sum(self.lbm.lbm_reduce_workspace_bytes(h["sol"].domain.layout) for h in hs)

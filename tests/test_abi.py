@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     lib = lbm.load()
     for name in declared_functions():
         assert hasattr(lib, name), name
-    assert lbm.lbm_abi_version() == 4
+    assert lbm.lbm_abi_version() == 5
 
 
 def test_struct_sizes_match_header_layout():
@@ -68,9 +68,9 @@ def _fake_state(q=19, nf=100, S=128, storage=lbm.STORE_F32):
     return st
 
 
-def expect(code, fn, *args):
+def expect(code, fn, *args, **kw):
     with pytest.raises(lbm.LbmError) as e:
-        fn(*args)
+        fn(*args, **kw)
     assert e.value.code == code
 
 
@@ -138,10 +138,28 @@ def test_batch_mismatch_rejected_on_host():
     a = _fake_state(storage=lbm.STORE_F32)
     b = _fake_state(storage=lbm.STORE_F64)
     c = lbm.collision()
-    expect(lbm.LBM_ESTATE, lbm.lbm_step_batch, [a, b], [c, c], None, 1, 0)
+    ws = dict(workspace=16, workspace_bytes=1 << 20)
+    expect(lbm.LBM_ESTATE, lbm.lbm_step_batch, [a, b], [c, c], None, 1, 0, **ws)
     b = _fake_state(storage=lbm.STORE_F32)
     b.t = 1
-    expect(lbm.LBM_ESTATE, lbm.lbm_step_batch, [a, b], [c, c], None, 1, 0)
+    expect(lbm.LBM_ESTATE, lbm.lbm_step_batch, [a, b], [c, c], None, 1, 0, **ws)
+
+
+def test_batch_workspace_checked_on_host():
+    """Several states need a workspace of the queried size (their segment
+    table); the size check comes before any device work."""
+    assert lbm.lbm_step_batch_workspace_bytes(0) == 0
+    one = lbm.lbm_step_batch_workspace_bytes(1)
+    assert one >= 2 * 128 and one % 256 == 0
+    n = 100
+    need = lbm.lbm_step_batch_workspace_bytes(n)
+    assert need >= 2 * n * 128 and need % 256 == 0 and need > one
+    states = [_fake_state() for _ in range(n)]
+    c = lbm.collision()
+    expect(lbm.LBM_EINVAL, lbm.lbm_step_batch, states, [c] * n, None, 1, 0, workspace=0,
+           workspace_bytes=0)
+    expect(lbm.LBM_ENOMEM, lbm.lbm_step_batch, states, [c] * n, None, 1, 0, workspace=16,
+           workspace_bytes=need - 1)
 
 
 def test_launch_table_roundtrip():

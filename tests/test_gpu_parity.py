@@ -430,6 +430,42 @@ def test_full_size_packing_two_steps_fp32(packing256, order, form):
         assert np.max(np.abs(got - ref) / ref) <= 1e-5
 
 
+def test_full_size_packing_fp64_100_steps(packing256):
+    """The benchmark's headline configuration, exactly as bench.py times it:
+    256^3 packing at porosity 0.6 (10.06 M fluid cells), D3Q19 TRT FP64,
+    blocked order, run-compressed index-list only (int32 list dropped),
+    default launch table.  100 AA steps from a perturbed state match the
+    oracle's sparse AA scheme within 1e-12 relative on every fluid cell."""
+    lab, per, info, _ = packing256
+    q = 19
+    _say("full size FP64 100 steps", info["n_fluid"])
+    ref_lay = oracle.sparse_build(lab, per, q, order=lbm.ORDER_BLOCKED, align=64)
+    coll, _, op = _params(q, lbm.COLL_TRT, 0.8, (1e-6, 0, 0), [])
+    dom = lbm.SparseDomain(lab, per, q, lbm.ORDER_BLOCKED)
+    dom.compact_runs(drop_index=True)
+    torch.cuda.synchronize()
+    assert dom.n_fluid == ref_lay.n_fluid and dom.stride == ref_lay.stride
+    assert np.array_equal(ref_lay.cells, dom.cells[:dom.n_fluid].cpu().numpy())
+    sol = lbm.Solver(dom, lbm.STORE_F64)
+    f0 = _random_state(q, dom.n_fluid, seed=17, amp=1e-3)
+    seen = _upload(sol, f0, 0)
+    del f0
+    S, nf = ref_lay.stride, dom.n_fluid
+    pdf = np.zeros(q * S)
+    for i in range(q):
+        pdf[i * S:i * S + nf] = seen[i]
+    del seen
+    sol.step(100, coll)
+    pdf = oracle.sparse_run(op, ref_lay, pdf, 0, 100)
+    torch.cuda.synchronize()
+    assert sol.t == 100
+    got = sol.pdf[:q * S].cpu().numpy().reshape(q, S)[:, :nf]
+    ref = pdf.reshape(q, S)[:, :nf]
+    err = float(np.max(np.abs(got - ref) / np.abs(ref)))
+    _say("full size FP64 max rel err", err)
+    assert err <= 1e-12
+
+
 @pytest.mark.parametrize("phi", [0.4, 0.95])
 def test_full_size_packing_other_porosities(phi):
     """The benchmark's other 256^3 porosities (6.7 M and 15.9 M fluid cells)
@@ -764,13 +800,18 @@ def test_runs_batch_mixes_index_forms():
 
 
 def test_batch_of_many_solves_matches_each_alone():
-    """40 small solves of different sizes, index forms and boundary classes
-    (one launch carries up to 64): batched steps and batched FP64
-    reductions equal each solve stepped and reduced alone, bit for bit."""
+    """150 small solves of different sizes, index forms and boundary classes
+    (one with no fluid cell), more than a kernel-argument table could hold:
+    one launch per step and form reads the segment table from the batch
+    workspace; batched steps and batched FP64 reductions equal each solve
+    stepped and reduced alone, bit for bit."""
+    n = 150
     coll, bs, _ = _params(19, lbm.COLL_TRT, 0.7, (1e-5, 0, 0), CLASSES)
     labs = [inputs.random_mask((6 + j % 5, 7 + j % 3, 5 + j % 4), 0.3, seed=200 + j,
                                n_classes=3 if j % 3 == 0 else 0, class_fraction=0.5)
-            for j in range(40)]
+            for j in range(n)]
+    labs[7] = np.ones_like(labs[7])
+    _say("batch of", n, "solves")
     out = []
     for batched in (False, True):
         sols = []
@@ -778,16 +819,21 @@ def test_batch_of_many_solves_matches_each_alone():
             dom = lbm.SparseDomain(lab, 3 if j % 3 == 0 else 7, 19, lbm.ORDER_BLOCKED)
             if j % 4 == 1:
                 dom.compact()
-            elif j % 4 == 2:
+            elif j % 4 == 2 and dom.n_fluid > 0:
                 dom.compact_runs(drop_index=True)
             s = lbm.Solver(dom, lbm.STORE_F32)
-            _upload(s, _random_state(19, dom.n_fluid, seed=j + 50), 0)
+            if dom.n_fluid > 0:
+                _upload(s, _random_state(19, dom.n_fluid, seed=j + 50), 0)
+            else:
+                s.init()
             sols.append(s)
         if batched:
-            lbm.lbm_step_batch([s.state for s in sols], [coll] * 40, [bs] * 40, 5)
+            ws = torch.empty(lbm.lbm_step_batch_workspace_bytes(n), dtype=torch.uint8,
+                             device="cuda")
+            lbm.lbm_step_batch([s.state for s in sols], [coll] * n, [bs] * n, 5, workspace=ws)
             ws = torch.empty(sum(lbm.lbm_reduce_workspace_bytes(s.domain.layout) for s in sols),
                              dtype=torch.uint8, device="cuda")
-            red = lbm.lbm_reduce_batch([s.state for s in sols], [coll] * 40, ws)
+            red = lbm.lbm_reduce_batch([s.state for s in sols], [coll] * n, ws)
         else:
             for s in sols:
                 s.step(5, coll, bs)
@@ -994,6 +1040,43 @@ def test_pull_scheme_bitwise_equals_aa(compact, kind):
     a.step(2, coll, bs)
     torch.cuda.synchronize()
     assert torch.equal(a.pdf.view(19, S)[:, :nf], b.pdf.view(19, S)[:, :nf])
+
+
+@pytest.mark.parametrize("storage,compact,kind", [(lbm.STORE_F64, False, lbm.COLL_TRT),
+                                                  (lbm.STORE_F32, False, lbm.COLL_TRT),
+                                                  (lbm.STORE_F64, True, lbm.COLL_MRT),
+                                                  (lbm.STORE_F32DEV, True, lbm.COLL_SRT)])
+def test_pull_scheme_matches_dense_oracle(storage, compact, kind):
+    """The two-array pull kernel against the oracle's dense pull scheme (the
+    same scheme, written independently): 10 steps with inlet (UBB) and
+    outlet (pressure) links on a partly periodic random packing, within
+    1e-12 relative in FP64 and 1e-5 in FP32 storage on every fluid cell."""
+    _say("pull vs oracle", storage, compact, kind)
+    q = 19
+    lab = inputs.random_mask((21, 17, 19), 0.3, seed=31 + kind, n_classes=3,
+                             class_fraction=0.5)
+    per = 5
+    coll, bs, op = _params(q, kind, 0.7, (2e-5, -1e-5, 5e-6), CLASSES)
+    dom = lbm.SparseDomain(lab, per, q, lbm.ORDER_BLOCKED)
+    if compact:
+        dom.compact()
+    torch.cuda.synchronize()
+    _check_index(dom)
+    assert dom.n_links > 0
+    sol = lbm.Solver(dom, storage)
+    seen = _upload(sol, _random_state(q, dom.n_fluid, seed=5 + kind), 0)
+    cells = dom.cells[:dom.n_fluid].cpu().numpy()
+    A = _dense_from_list(seen, cells, lab.shape, q)
+    tol = 1e-12 if storage == lbm.STORE_F64 else 1e-5
+    for n in (2, 8):
+        sol.step_pull(n, coll, bs)
+        A = oracle.dense_run(op, lab, per, n, A)
+        torch.cuda.synchronize()
+        got = _download(sol, 0)
+        ref = A.reshape(q, -1)[:, cells]
+        err = float(np.max(np.abs(got - ref) / np.abs(ref)))
+        assert err <= tol, (sol.t, err)
+    assert sol.t == 10
 
 
 # ------------------------------------------------------------ vessel tree

@@ -111,3 +111,69 @@ def test_refinement_reaches_fp32_accuracy_and_stays_batch_independent():
     for a, b in zip(mixed, alone):
         assert (a.steps, a.refined_at, a.converged) == (b.steps, b.refined_at, b.converged)
         assert a.permeability == b.permeability
+
+
+class _SimClockStepper(server.GpuStepper):
+    """GpuStepper on a simulated clock: a round of n steps advances the clock
+    by a fixed amount per solve, and a request's geometry counts as ready
+    once generated, so admissions happen at the same rounds in every run.
+    Records, for each build, how many solves were being stepped."""
+
+    def __init__(self, **kw):
+        super().__init__(**kw)
+        self.now = 0.0
+        self.live = 0
+        self.builds = []
+
+    def clock(self):
+        return self.now
+
+    def sleep(self, dt):
+        self.now += dt
+
+    def ready(self, r):
+        self.prepare(r)
+        self._labels[r.rid].result()
+        return True
+
+    def step(self, hs, n):
+        self.live = len(hs)
+        super().step(hs, n)
+        self.now += 0.01 * len(hs) * n / 100
+
+    def build(self, r):
+        self.builds.append((r.rid, self.live))
+        return super().build(r)
+
+    def free(self, h):
+        self.live -= 1
+        super().free(h)
+
+
+def test_requests_joining_mid_flight_equal_alone():
+    """Staggered arrivals on a simulated clock: later requests are admitted
+    and built (on the side stream) while earlier ones are stepping, and
+    16-bit solves are refined to FP32 deviations in the same rounds (their
+    old PDF-lists released while builds run).  Every result -- step count,
+    refinement step, permeability -- is bitwise that of the request served
+    alone."""
+    def trace():
+        reqs = server.make_trace(6, 1000.0, seed=9, L_range=(24, 40), phi_range=(0.4, 0.8))
+        for j, r in enumerate(reqs):
+            r.arrival = 0.03 * j
+            r.force = 1e-5
+        return reqs
+
+    st = _SimClockStepper(storage=lbm.STORE_F16DEV)
+    mixed, met = server.Server(st, 1 << 34, K=100, tol=1e-6, max_steps=3000, refine_tol=1e-4,
+                               clock=st.clock, sleep=st.sleep).run(trace())
+    alone, _ = server.run_sequential(server.GpuStepper(storage=lbm.STORE_F16DEV), trace(),
+                                     K=100, tol=1e-6, max_steps=3000, refine_tol=1e-4)
+    print(f"[gpu-test] builds (rid, solves stepping): {st.builds}", flush=True)
+    assert met["completed"] == 6
+    assert any(live > 0 for _, live in st.builds[1:])     # joins during stepping
+    assert any(a.refined_at for a in mixed)
+    for a, b in zip(mixed, alone):
+        assert (a.rid, a.steps, a.refined_at, a.converged) == (b.rid, b.steps, b.refined_at,
+                                                                b.converged)
+        assert a.permeability == b.permeability
