@@ -144,12 +144,12 @@ hipError_t launch_links(int storage, const LinkArgs& a, hipStream_t st) {
 // decodes runs a whole wave at a time instead.
 __device__ __forceinline__ uint32_t run_pos(const Seg& g, int q, int i, uint32_t k) {
   const uint32_t w = k / kRunWave, lane = k % kRunWave;
-  const uint64_t* mk = g.rmask + (size_t)w * (q - 1);
-  uint32_t vb = g.rvoff[w];
+  const LBM_GLOBAL uint64_t* mk = gp(g.rmask) + (size_t)w * (q - 1);
+  uint32_t vb = gp(g.rvoff)[w];
   for (int d = 1; d < i; ++d) vb += (uint32_t)__popcll(mk[d - 1]);
   const uint64_t upto = lane == kRunWave - 1 ? ~0ull : ((2ull << lane) - 1ull);
   const uint32_t r = (uint32_t)__popcll(mk[i - 1] & upto) - 1u;
-  return (uint32_t)g.rval[vb + r] + lane;
+  return (uint32_t)gp(g.rval)[vb + r] + lane;
 }
 
 // Post-collision deviations of cell k at the current time in natural order.
@@ -161,7 +161,7 @@ __device__ __forceinline__ void gather_post(const Seg& g, uint32_t k,
   using SP = Store<ST>;
   using T = typename SP::T;
   using R = typename SP::R;
-  const T* pdf = static_cast<const T*>(g.pdf);
+  const LBM_GLOBAL T* pdf = gp(static_cast<const T*>(g.pdf));
   const R isc = R(g.inv_scale);
   const uint32_t t16 = k / kTile16;
 #pragma unroll
@@ -170,7 +170,7 @@ __device__ __forceinline__ void gather_post(const Seg& g, uint32_t k,
     if (ODD_T && j > 0)
       pos = g.rval    ? run_pos(g, Q, opp(j), k)
             : g.off16 ? pos16(g, Q, opp(j), j, k, t16)
-                      : (uint32_t)g.idx[(size_t)(opp(j) - 1) * g.S + k];
+                      : (uint32_t)gp(g.idx)[(size_t)(opp(j) - 1) * g.S + k];
     else
       pos = (uint32_t)j * g.S + k;
     d[j] = SP::load(pdf[pos], R(Lattice<Q>::w(j)), isc);
@@ -250,16 +250,13 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Sums of one thread's cell of a reduction tile into v (zeros past the
+// segment's fluid cells).
 template <int Q, int ST, bool ODD_T>
-__global__ __launch_bounds__(kRedBlock) void k_reduce_tiles(const StepArgs a, double* partials) {
+__device__ __forceinline__ void reduce_cell(const Seg& g, uint32_t tile, double (&v)[5]) {
   using R = typename Store<ST>::R;
   using L = Lattice<Q>;
-  __shared__ double sh[kRedBlock / 64][5];
-  const uint32_t tile = blockIdx.x;
-  const int s = seg_of(a, tile);
-  const Seg& g = seg_at(a, s);
   const uint32_t k = (tile - g.tile0) * kRedBlock + threadIdx.x;
-  double v[5] = {0, 0, 0, 0, 0};
   if (k < g.nf) {
     R d[Q];
     gather_post<Q, ST, ODD_T>(g, k, d);
@@ -279,6 +276,14 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce_tiles(const StepArgs a, do
     for (int m = 0; m < 4; ++m) fin = fin && __builtin_isfinite(v[m]);
     v[4] = fin ? 0.0 : 1.0;
   }
+}
+
+template <int Q, int ST, bool ODD_T>
+__global__ __launch_bounds__(kRedBlock) void k_reduce_tiles(const StepArgs a, double* partials) {
+  __shared__ double sh[kRedBlock / 64][5];
+  const uint32_t tile = blockIdx.x;
+  double v[5] = {0, 0, 0, 0, 0};
+  with_seg(a, tile, [&](const Seg& g) { reduce_cell<Q, ST, ODD_T>(g, tile, v); });
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
@@ -297,8 +302,8 @@ __global__ __launch_bounds__(256) void k_reduce_segs(const StepArgs a, const dou
                                                      double* out) {
   __shared__ double sh[256][5];
   const int s = blockIdx.x;
-  const uint32_t t0 = seg_at(a, s).tile0;
-  const uint32_t t1 = (s + 1 < a.nseg) ? seg_at(a, s + 1).tile0 : a.ntiles;
+  const uint32_t t0 = seg_tile0(a, s);
+  const uint32_t t1 = (s + 1 < a.nseg) ? seg_tile0(a, s + 1) : a.ntiles;
   double v[5] = {0, 0, 0, 0, 0};
   for (uint32_t t = t0 + threadIdx.x; t < t1; t += 256)
     for (int m = 0; m < 5; ++m) v[m] += partials[(size_t)t * 5 + m];
@@ -310,7 +315,7 @@ __global__ __launch_bounds__(256) void k_reduce_segs(const StepArgs a, const dou
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const double nf = (double)seg_at(a, s).nf;
+    const double nf = (double)seg_nf(a, s);
     out[s * 8 + 0] = nf + sh[0][0];  // mass
     out[s * 8 + 1] = sh[0][0];       // sum of density deviations
     out[s * 8 + 2] = sh[0][1];

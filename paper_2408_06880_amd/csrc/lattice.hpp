@@ -157,19 +157,36 @@ struct StepArgs {
   Seg seg0;                // the segment when nseg == 1
 };
 
-// Segment s of a launch.
-__device__ __forceinline__ const Seg& seg_at(const StepArgs& a, int s) {
-  return a.nseg == 1 ? a.seg0 : a.segs[s];
+// Global-memory pointers.  Pointers in kernel arguments are known to the
+// compiler to address global memory; a pointer read from a device table (a
+// batch's segment table) is generic to it, and generic pointers compile to
+// flat loads and stores, which are slower.  Kernels convert every buffer
+// pointer of a segment with gp() before using it.  (The host compilation
+// pass sees the same source without the address space.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define LBM_GLOBAL __attribute__((address_space(1)))
+#else
+#define LBM_GLOBAL
+#endif
+
+template <class T>
+__device__ __forceinline__ LBM_GLOBAL T* gp(T* p) {
+  return (LBM_GLOBAL T*)p;
+}
+template <class T>
+__device__ __forceinline__ const LBM_GLOBAL T* gp(const T* p) {
+  return (const LBM_GLOBAL T*)p;
 }
 
 // Pull position of population i of cell k from the compact index-list
 // (t16 = the cell's compact tile; tile bases are stored [tile][direction]).
 __device__ __forceinline__ uint32_t pos16(const Seg& g, int q, int i, int oi, uint32_t k,
                                           uint32_t t16) {
-  const uint16_t o = g.off16[(size_t)(i - 1) * g.S + k];
-  const int32_t b = g.base16[(size_t)t16 * (q - 1) + (i - 1)];
+  const uint16_t o = gp(g.off16)[(size_t)(i - 1) * g.S + k];
+  const int32_t b = gp(g.base16)[(size_t)t16 * (q - 1) + (i - 1)];
   if (o >= kEscape16)
-    return o == kBounce16 ? (uint32_t)oi * g.S + k : (uint32_t)g.idx[(size_t)(i - 1) * g.S + k];
+    return o == kBounce16 ? (uint32_t)oi * g.S + k
+                          : (uint32_t)gp(g.idx)[(size_t)(i - 1) * g.S + k];
   return (uint32_t)i * g.S + k + (uint32_t)b + (uint32_t)o;
 }
 
@@ -196,6 +213,28 @@ __device__ __forceinline__ int seg_of(const StepArgs& a, uint32_t tile) {
       hi = mid - 1;
   }
   return lo;
+}
+
+// Calls f(segment that owns `tile`).  A single segment is read from the
+// kernel arguments, one of several from the device table; the two calls are
+// kept apart (rather than selecting between the two sources) so that the
+// segment's fields load with scalar loads on both paths.
+template <class F>
+__device__ __forceinline__ void with_seg(const StepArgs& a, uint32_t tile, F&& f) {
+  if (a.nseg == 1) {
+    f(a.seg0);
+  } else {
+    const Seg g = a.segs[seg_of(a, tile)];
+    f(g);
+  }
+}
+
+// First tile and fluid cells of segment s.
+__device__ __forceinline__ uint32_t seg_tile0(const StepArgs& a, int s) {
+  return a.nseg == 1 ? a.seg0.tile0 : a.segs[s].tile0;
+}
+__device__ __forceinline__ uint32_t seg_nf(const StepArgs& a, int s) {
+  return a.nseg == 1 ? a.seg0.nf : a.segs[s].nf;
 }
 
 }  // namespace lbm

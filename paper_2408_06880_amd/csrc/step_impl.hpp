@@ -76,7 +76,7 @@ __device__ __forceinline__ CollParams<R> seg_params(const Seg& g) {
 #endif
 
 template <bool NT, class T>
-__device__ __forceinline__ T ld(const T* p) {
+__device__ __forceinline__ T ld(const LBM_GLOBAL T* p) {
   if constexpr (NT)
     return __builtin_nontemporal_load(p);
   else
@@ -84,7 +84,7 @@ __device__ __forceinline__ T ld(const T* p) {
 }
 
 template <bool NT, class T>
-__device__ __forceinline__ void st(T v, T* p) {
+__device__ __forceinline__ void st(T v, LBM_GLOBAL T* p) {
   if constexpr (NT)
     __builtin_nontemporal_store(v, p);
   else
@@ -99,8 +99,8 @@ template <int Q>
 __device__ __forceinline__ void run_positions(const Seg& g, uint32_t k, uint32_t (&pos)[Q]) {
   const uint32_t lane = threadIdx.x & (kRunWave - 1);
   const uint32_t w = __builtin_amdgcn_readfirstlane(k / kRunWave);
-  const uint64_t* __restrict__ mk = g.rmask + (size_t)w * (Q - 1);
-  const int32_t* __restrict__ val = g.rval + g.rvoff[w];
+  const LBM_GLOBAL uint64_t* __restrict__ mk = gp(g.rmask) + (size_t)w * (Q - 1);
+  const LBM_GLOBAL int32_t* __restrict__ val = gp(g.rval) + gp(g.rvoff)[w];
   uint32_t vb = 0;
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
@@ -113,19 +113,17 @@ __device__ __forceinline__ void run_positions(const Seg& g, uint32_t k, uint32_t
   }
 }
 
+// One cell of an AA (or pull) step; `tile` is the workgroup's tile of the
+// launch and g the segment that owns it.
 template <int Q, int COLL, int ST, int MODE, int IDX>
-__global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU))) void k_aa_step(const StepArgs a) {
+__device__ __forceinline__ void aa_cell(const Seg& g, uint32_t tile) {
   constexpr bool GATHER = MODE != MODE_EVEN;
   using SP = Store<ST>;
   using T = typename SP::T;
   using R = typename SP::R;
-  const uint32_t tile = a.xcd_remap ? xcd_tile(blockIdx.x, a.ntiles) : blockIdx.x;
-  const int s = seg_of(a, tile);
-  const Seg g = seg_at(a, s);
   const uint32_t k = (tile - g.tile0) * blockDim.x + threadIdx.x;
   if (k >= g.nf) return;
-  T* __restrict__ pdf = static_cast<T*>(g.pdf);
+  LBM_GLOBAL T* __restrict__ pdf = gp(static_cast<T*>(g.pdf));
   const uint32_t S = g.S;
   const R sc = R(g.scale), isc = R(g.inv_scale);
   R d[Q];
@@ -138,9 +136,9 @@ __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU))) void k_aa_step(const
       // All offset loads first, then the tile's bases (the workgroup lies in
       // one compact tile: the block size divides kTile16), then branch-free
       // positions; escaped entries are patched under a wave-uniform branch.
-      const uint16_t* __restrict__ off = g.off16;
+      const LBM_GLOBAL uint16_t* __restrict__ off = gp(g.off16);
       const uint32_t t16 = ((tile - g.tile0) * blockDim.x) / kTile16;
-      const int32_t* __restrict__ base = g.base16 + (size_t)t16 * (Q - 1);
+      const LBM_GLOBAL int32_t* __restrict__ base = gp(g.base16) + (size_t)t16 * (Q - 1);
       uint32_t o[Q];
       int32_t b[Q];
 #pragma unroll
@@ -157,13 +155,13 @@ __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU))) void k_aa_step(const
         esc = esc || o[i] == kEscape16;
       }
       if (__ballot(esc)) {
-        const int32_t* __restrict__ idx = g.idx;
+        const LBM_GLOBAL int32_t* __restrict__ idx = gp(g.idx);
 #pragma unroll
         for (int i = 1; i < Q; ++i)
           if (o[i] == kEscape16) pos[i] = (uint32_t)idx[(size_t)(i - 1) * S + k];
       }
     } else {
-      const int32_t* __restrict__ idx = g.idx;
+      const LBM_GLOBAL int32_t* __restrict__ idx = gp(g.idx);
 #pragma unroll
       for (int i = 1; i < Q; ++i)
         pos[i] = static_cast<uint32_t>(ld<LBM_NT_INDEX>(idx + (size_t)(i - 1) * S + k));
@@ -177,7 +175,7 @@ __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU))) void k_aa_step(const
       for (int i = 0; i < Q; ++i)
         st<LBM_NT_SCATTER>(SP::store(d[opp(i)], R(Lattice<Q>::w(i)), sc), pdf + pos[i]);
     } else {
-      T* __restrict__ dst = static_cast<T*>(g.dst);
+      LBM_GLOBAL T* __restrict__ dst = gp(static_cast<T*>(g.dst));
 #pragma unroll
       for (int i = 0; i < Q; ++i)
         __builtin_nontemporal_store(SP::store(d[i], R(Lattice<Q>::w(i)), sc),
@@ -196,6 +194,13 @@ __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU))) void k_aa_step(const
   }
 }
 
+template <int Q, int COLL, int ST, int MODE, int IDX>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU))) void k_aa_step(const StepArgs a) {
+  const uint32_t tile = a.xcd_remap ? xcd_tile(blockIdx.x, a.ntiles) : blockIdx.x;
+  with_seg(a, tile, [&](const Seg& g) { aa_cell<Q, COLL, ST, MODE, IDX>(g, tile); });
+}
+
 // Even step, two neighbouring cells per thread: every load and store moves a
 // 2-vector (cells k, k+1 of one direction block), twice the bytes per
 // memory instruction of the one-cell kernel.  v[j] holds slot j of both
@@ -205,24 +210,22 @@ __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU))) void k_aa_step(const
 // odd, the last pair's second cell is a padding slot (k+1 < stride): it
 // collides its own finite padding values, which only padding reads.
 template <int Q, int COLL, int ST>
-__global__ __launch_bounds__(256) void k_even_pair(const StepArgs a) {
+__device__ __forceinline__ void even_pair_cells(const Seg& g, uint32_t tile) {
   using SP = Store<ST>;
   using T = typename SP::T;
   using R = typename SP::R;
   typedef T T2 __attribute__((ext_vector_type(2)));
-  const uint32_t tile = a.xcd_remap ? xcd_tile(blockIdx.x, a.ntiles) : blockIdx.x;
-  const int s = seg_of(a, tile);
-  const Seg g = seg_at(a, s);
   const uint32_t k = 2 * ((tile - g.tile0) * blockDim.x + threadIdx.x);
   if (k >= g.nf) return;
-  T* __restrict__ pdf = static_cast<T*>(g.pdf);
+  LBM_GLOBAL T* __restrict__ pdf = gp(static_cast<T*>(g.pdf));
   const uint32_t S = g.S;
   const R sc = R(g.scale), isc = R(g.inv_scale);
   const CollParams<R> p = seg_params<R>(g);
   T2 v[Q];
 #pragma unroll
   for (int j = 0; j < Q; ++j)
-    v[j] = __builtin_nontemporal_load(reinterpret_cast<const T2*>(pdf + (size_t)j * S + k));
+    v[j] = __builtin_nontemporal_load(
+        reinterpret_cast<const LBM_GLOBAL T2*>(pdf + (size_t)j * S + k));
   R d[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) d[i] = SP::load(v[opp(i)].x, R(Lattice<Q>::w(i)), isc);
@@ -236,7 +239,13 @@ __global__ __launch_bounds__(256) void k_even_pair(const StepArgs a) {
   for (int i = 0; i < Q; ++i) v[i].y = SP::store(d[i], R(Lattice<Q>::w(i)), sc);
 #pragma unroll
   for (int j = 0; j < Q; ++j)
-    __builtin_nontemporal_store(v[j], reinterpret_cast<T2*>(pdf + (size_t)j * S + k));
+    __builtin_nontemporal_store(v[j], reinterpret_cast<LBM_GLOBAL T2*>(pdf + (size_t)j * S + k));
+}
+
+template <int Q, int COLL, int ST>
+__global__ __launch_bounds__(256) void k_even_pair(const StepArgs a) {
+  const uint32_t tile = a.xcd_remap ? xcd_tile(blockIdx.x, a.ntiles) : blockIdx.x;
+  with_seg(a, tile, [&](const Seg& g) { even_pair_cells<Q, COLL, ST>(g, tile); });
 }
 
 // Persistent, software-pipelined odd step (compact index-list).  Each
@@ -246,10 +255,11 @@ __global__ __launch_bounds__(256) void k_even_pair(const StepArgs a) {
 // so the index latency of one tile overlaps the gather/collide/scatter of
 // the previous one.  Same arithmetic as k_aa_step<..., MODE_ODD, true>.
 template <int Q>
-__device__ __forceinline__ void pipe_load_offsets(const Seg& g, uint32_t k, uint32_t (&o)[Q]) {
+__device__ __forceinline__ void pipe_load_offsets(const Seg& g, uint32_t tile, uint32_t (&o)[Q]) {
+  const uint32_t k = (tile - g.tile0) * blockDim.x + threadIdx.x;
   if (k < g.nf) {
 #pragma unroll
-    for (int i = 1; i < Q; ++i) o[i] = ld<LBM_NT_INDEX>(g.off16 + (size_t)(i - 1) * g.S + k);
+    for (int i = 1; i < Q; ++i) o[i] = ld<LBM_NT_INDEX>(gp(g.off16) + (size_t)(i - 1) * g.S + k);
   }
 }
 
@@ -262,33 +272,25 @@ __global__ __launch_bounds__(256) void k_odd_pipe(const StepArgs a) {
   uint32_t v = blockIdx.x;
   if (v >= a.ntiles) return;
   uint32_t tile = a.xcd_remap ? xcd_tile(v, a.ntiles) : v;
-  int s = seg_of(a, tile);
   uint32_t o[Q];
-  {
-    const Seg g = seg_at(a, s);
-    pipe_load_offsets<Q>(g, (tile - g.tile0) * blockDim.x + threadIdx.x, o);
-  }
+  with_seg(a, tile, [&](const Seg& g) { pipe_load_offsets<Q>(g, tile, o); });
   while (true) {
     const uint32_t vn = v + G;
     const bool has_next = vn < a.ntiles;
     uint32_t tn = 0;
-    int sn = 0;
     uint32_t on[Q];
     if (has_next) {
       tn = a.xcd_remap ? xcd_tile(vn, a.ntiles) : vn;
-      sn = seg_of(a, tn);
-      const Seg gn = seg_at(a, sn);
-      pipe_load_offsets<Q>(gn, (tn - gn.tile0) * blockDim.x + threadIdx.x, on);
+      with_seg(a, tn, [&](const Seg& gn) { pipe_load_offsets<Q>(gn, tn, on); });
     }
-    {
-      const Seg g = seg_at(a, s);
+    with_seg(a, tile, [&](const Seg& g) {
       const uint32_t k = (tile - g.tile0) * blockDim.x + threadIdx.x;
       if (k < g.nf) {
-        T* __restrict__ pdf = static_cast<T*>(g.pdf);
+        LBM_GLOBAL T* __restrict__ pdf = gp(static_cast<T*>(g.pdf));
         const uint32_t S = g.S;
         const R sc = R(g.scale), isc = R(g.inv_scale);
         const uint32_t t16 = ((tile - g.tile0) * blockDim.x) / kTile16;
-        const int32_t* __restrict__ base = g.base16 + (size_t)t16 * (Q - 1);
+        const LBM_GLOBAL int32_t* __restrict__ base = gp(g.base16) + (size_t)t16 * (Q - 1);
         uint32_t pos[Q];
         int32_t b[Q];
         pos[0] = k;
@@ -306,7 +308,7 @@ __global__ __launch_bounds__(256) void k_odd_pipe(const StepArgs a) {
         if (__ballot(esc)) {
 #pragma unroll
           for (int i = 1; i < Q; ++i)
-            if (o[i] == kEscape16) pos[i] = (uint32_t)g.idx[(size_t)(i - 1) * S + k];
+            if (o[i] == kEscape16) pos[i] = (uint32_t)gp(g.idx)[(size_t)(i - 1) * S + k];
         }
         R d[Q];
 #pragma unroll
@@ -317,11 +319,10 @@ __global__ __launch_bounds__(256) void k_odd_pipe(const StepArgs a) {
         for (int i = 0; i < Q; ++i)
           st<LBM_NT_SCATTER>(SP::store(d[opp(i)], R(Lattice<Q>::w(i)), sc), pdf + pos[i]);
       }
-    }
+    });
     if (!has_next) break;
     v = vn;
     tile = tn;
-    s = sn;
 #pragma unroll
     for (int i = 1; i < Q; ++i) o[i] = on[i];
   }
