@@ -30,6 +30,11 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* Loops over fewer cells than this run on one thread: on tiny test boxes a
+ * parallel region per step costs more than the step.  Every cell is
+ * computed on its own, so the thread count never changes a result. */
+#define ORC_PAR_MIN 32768
+
 /* ------------------------------------------------------------------ */
 /* Velocity sets.                                                      */
 /* D3Q19 / D3Q27 with the pairwise order: 0 rest, then (+e,-e) pairs:  */
@@ -411,25 +416,31 @@ static void orc_collide_mrt(const orc_stencil* s, const orc_params* P, const dou
                             double* out) {
   double rho, u[3];
   orc_macros(s, f, P->force, &rho, u);
+  /* equilibrium, Guo source and squared row norms, each computed once */
+  double feq[19], src[19], norm[19];
+  for (int i = 0; i < 19; ++i) {
+    feq[i] = orc_feq(s, i, rho, u);
+    src[i] = orc_guo(s, i, u, P->force);
+  }
+  for (int k = 0; k < 19; ++k) {
+    norm[k] = 0.0;
+    for (int j = 0; j < 19; ++j) norm[k] += orc_mrt_poly(k, s->c[j]) * orc_mrt_poly(k, s->c[j]);
+  }
   double mstar[19];
   for (int k = 0; k < 19; ++k) {
     double m = 0.0, meq = 0.0, ms = 0.0;
     for (int i = 0; i < 19; ++i) {
       double pk = orc_mrt_poly(k, s->c[i]);
       m += pk * f[i];
-      meq += pk * orc_feq(s, i, rho, u);
-      ms += pk * orc_guo(s, i, u, P->force);
+      meq += pk * feq[i];
+      ms += pk * src[i];
     }
     double sk = orc_mrt_rate(P, k);
     mstar[k] = m - sk * (m - meq) + (1.0 - 0.5 * sk) * ms;
   }
   for (int i = 0; i < 19; ++i) {
     double acc = 0.0;
-    for (int k = 0; k < 19; ++k) {
-      double norm = 0.0;
-      for (int j = 0; j < 19; ++j) norm += orc_mrt_poly(k, s->c[j]) * orc_mrt_poly(k, s->c[j]);
-      acc += orc_mrt_poly(k, s->c[i]) * mstar[k] / norm;
-    }
+    for (int k = 0; k < 19; ++k) acc += orc_mrt_poly(k, s->c[i]) * mstar[k] / norm[k];
     out[i] = acc;
   }
 }
@@ -520,7 +531,7 @@ int orc_dense_step(const orc_params* P, const uint8_t* labels, int nx, int ny, i
   if (P->kind == ORC_MRT && P->q != 19) return -1;
   const int64_t N = (int64_t)nx * ny * nz;
   const int q = s.q;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if ((int64_t)nx * ny * nz >= ORC_PAR_MIN)
   for (int z = 0; z < nz; ++z) {
     double f[27], fs[27];
     for (int y = 0; y < ny; ++y)
@@ -568,7 +579,7 @@ int orc_dense_init(int q, const uint8_t* labels, int64_t N, double rho0, const d
   if (orc_stencil_init(&s, q)) return -1;
   for (int i = 0; i < q; ++i) {
     const double feq = orc_feq(&s, i, rho0, u0);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (N >= ORC_PAR_MIN)
     for (int64_t lin = 0; lin < N; ++lin) A[i * N + lin] = labels[lin] == 0 ? feq : s.w[i];
   }
   return 0;
@@ -787,7 +798,7 @@ int orc_sparse_step(const orc_params* P, int64_t n_fluid, int64_t S, const int32
   const int q = s.q;
   orc_sparse_links(&s, P, n_links, links, pdf);
   if ((t & 1) == 0) {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n_fluid >= ORC_PAR_MIN)
     for (int64_t k = 0; k < n_fluid; ++k) {
       double f[27], fs[27];
       int64_t pos[27];
@@ -798,7 +809,7 @@ int orc_sparse_step(const orc_params* P, int64_t n_fluid, int64_t S, const int32
       for (int i = 0; i < q; ++i) pdf[pos[i]] = fs[s.opp[i]];
     }
   } else {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n_fluid >= ORC_PAR_MIN)
     for (int64_t k = 0; k < n_fluid; ++k) {
       double f[27], fs[27];
       for (int i = 0; i < q; ++i) f[i] = pdf[(int64_t)s.opp[i] * S + k];
