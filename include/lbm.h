@@ -348,6 +348,27 @@ lbm_status lbm_step_batch(lbm_state* const* states, const lbm_collision* const* 
                           const lbm_bspec* const* bspecs, int32_t n_states, int32_t n_steps,
                           void* workspace, uint64_t workspace_bytes, void* stream);
 
+/* lbm_step_batch for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same steps, launches and results as lbm_step_batch with
+ * the same arguments, but the segment tables go into a fixed device array
+ * inside the library instead of a caller workspace.  The array holds the
+ * tables of LBM_STEP_BATCH_NOALLOC_MAX states (about 320 KiB); each device
+ * the library runs on keeps its own copy until the process ends, and the
+ * call allocates nothing.
+ *  n_states  1 .. LBM_STEP_BATCH_NOALLOC_MAX; more returns LBM_ENOMEM.
+ *  stream    must belong to the calling thread's current device
+ *            (LBM_EINVAL otherwise).
+ * Every call on one device writes that device's array (each call writes
+ * the whole table it reads before its first launch, so nothing is carried
+ * over), so calls whose launches may overlap on one device -- from several
+ * threads or on several streams without ordering between them -- race;
+ * serialise them.  Errors as lbm_step_batch. */
+#define LBM_STEP_BATCH_NOALLOC_MAX 1024
+lbm_status lbm_step_batch_noalloc(lbm_state* const* states, const lbm_collision* const* colls,
+                                  const lbm_bspec* const* bspecs, int32_t n_states,
+                                  int32_t n_steps, void* stream);
+
 /* Per-state reductions of lbm_reduce for n states at once (no limit on n),
  * bitwise equal to calling lbm_reduce on each.  workspace >= sum of
  * lbm_reduce_workspace_bytes over the states (it also holds the batch's
@@ -428,9 +449,9 @@ lbm_status lbm_copy(void* dst, const void* src, uint64_t bytes, void* stream);
 /* Message of the last failing call on the calling thread (owned by the
  * library, valid until that thread's next call; empty when none failed). */
 const char* lbm_last_error(void);
-/* Version of this interface: 5 (launch table with residency caps, unsigned
+/* Version of this interface: 6 (launch table with residency caps, unsigned
  * 32-bit positions, optional int32 index-list next to the run form, batch
- * segment tables in a caller workspace). */
+ * segment tables in a caller workspace, batch steps without allocation). */
 int32_t lbm_abi_version(void);
 
 #ifdef __cplusplus

@@ -302,7 +302,7 @@ uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); 
 
 extern "C" {
 
-int32_t lbm_abi_version(void) { return 5; }
+int32_t lbm_abi_version(void) { return 6; }
 
 const char* lbm_last_error(void) { return g_err.c_str(); }
 
@@ -682,9 +682,9 @@ uint64_t lbm_step_batch_workspace_bytes(int32_t n_states) {
   return 2 * seg_table_bytes(n_states);
 }
 
-lbm_status lbm_step_batch(lbm_state* const* states, const lbm_collision* const* colls,
-                          const lbm_bspec* const* bspecs, int32_t n, int32_t n_steps,
-                          void* workspace, uint64_t workspace_bytes, void* stream) {
+// Arguments of a batched step (both batch entry points).
+static lbm_status check_batch(lbm_state* const* states, const lbm_collision* const* colls,
+                              int32_t n, int32_t n_steps) {
   if (!states || !colls || n < 1) return fail(LBM_EINVAL, "lbm_step_batch: empty batch");
   if (n_steps < 0) return fail(LBM_EINVAL, "n_steps must be >= 0");
   for (int32_t j = 0; j < n; ++j) {
@@ -696,6 +696,14 @@ lbm_status lbm_step_batch(lbm_state* const* states, const lbm_collision* const* 
         ((states[j]->t ^ states[0]->t) & 1) || colls[j]->kind != colls[0]->kind)
       return fail(LBM_ESTATE, "batch member %d differs in q, storage, parity or collision kind", j);
   }
+  return LBM_OK;
+}
+
+lbm_status lbm_step_batch(lbm_state* const* states, const lbm_collision* const* colls,
+                          const lbm_bspec* const* bspecs, int32_t n, int32_t n_steps,
+                          void* workspace, uint64_t workspace_bytes, void* stream) {
+  lbm_status rc = check_batch(states, colls, n, n_steps);
+  if (rc) return rc;
   if (n > 1) {
     if (!workspace) return fail(LBM_EINVAL, "workspace is NULL");
     if (workspace_bytes < lbm_step_batch_workspace_bytes(n))
@@ -704,6 +712,64 @@ lbm_status lbm_step_batch(lbm_state* const* states, const lbm_collision* const* 
                   (unsigned long long)lbm_step_batch_workspace_bytes(n), n);
   }
   return step_group(states, colls, bspecs, n, n_steps, (Seg*)workspace, (hipStream_t)stream);
+}
+
+// ------------------------------------------- batch without allocation
+// Segment tables of lbm_step_batch_noalloc: room for
+// LBM_STEP_BATCH_NOALLOC_MAX states, one copy per device, held until the
+// process ends.  Host code must not pass `scratch` itself to a kernel (in
+// host code the name stands for a host-side shadow, not the device
+// address); it uses the address hipGetSymbolAddress returns for the device.
+constexpr uint64_t kScratchBytes =
+    2 * (((uint64_t)LBM_STEP_BATCH_NOALLOC_MAX * sizeof(Seg) + 255) / 256 * 256);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+// Device address of this device's `scratch`, looked up once per device
+// (with that device current) and kept.  The stream must belong to the
+// current device.
+static lbm_status scratch_table(hipStream_t st, void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(LBM_EINVAL, "device %d out of range", dev);
+  if (st) {
+    hipDevice_t sd = 0;
+    HIP_TRY(hipStreamGetDevice(st, &sd), "hipStreamGetDevice");
+    if ((int)sd != dev)
+      return fail(LBM_EINVAL, "the stream belongs to device %d, the current device is %d",
+                  (int)sd, dev);
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return LBM_OK;
+}
+
+lbm_status lbm_step_batch_noalloc(lbm_state* const* states, const lbm_collision* const* colls,
+                                  const lbm_bspec* const* bspecs, int32_t n, int32_t n_steps,
+                                  void* stream) {
+  if (n > LBM_STEP_BATCH_NOALLOC_MAX)
+    return fail(LBM_ENOMEM, "lbm_step_batch_noalloc takes at most %d states (got %d)",
+                LBM_STEP_BATCH_NOALLOC_MAX, n);
+  static_assert(2 * LBM_STEP_BATCH_NOALLOC_MAX * sizeof(Seg) <= kScratchBytes,
+                "scratch holds the segment tables of both parities");
+  lbm_status rc = check_batch(states, colls, n, n_steps);
+  if (rc) return rc;
+  void* table = nullptr;
+  if (n > 1 && n_steps > 0) {
+    rc = scratch_table((hipStream_t)stream, &table);
+    if (rc) return rc;
+  }
+  return step_group(states, colls, bspecs, n, n_steps, (Seg*)table, (hipStream_t)stream);
 }
 
 lbm_status lbm_moments(const lbm_state* s, const lbm_collision* c, int32_t out_f64, void* rho,

@@ -122,6 +122,10 @@ _SIGS = {
                               ctypes.POINTER(ctypes.POINTER(lbm_collision)),
                               ctypes.POINTER(ctypes.POINTER(lbm_bspec)), _i32, _i32, _vp, _u64,
                               _vp]),
+    "lbm_step_batch_noalloc": (_i32, [ctypes.POINTER(ctypes.POINTER(lbm_state)),
+                                      ctypes.POINTER(ctypes.POINTER(lbm_collision)),
+                                      ctypes.POINTER(ctypes.POINTER(lbm_bspec)), _i32, _i32,
+                                      _vp]),
     "lbm_reduce_batch": (_i32, [ctypes.POINTER(ctypes.POINTER(lbm_state)),
                                 ctypes.POINTER(ctypes.POINTER(lbm_collision)), _i32, _vp,
                                 ctypes.POINTER(lbm_reduction), _vp]),
@@ -310,6 +314,22 @@ def lbm_step_batch(states, colls, bspecs, n_steps, stream=None, workspace=None,
         nbytes = 0
     _call("lbm_step_batch", sp, cp, bp, n, int(n_steps), _ptr(workspace), nbytes,
           _stream(stream))
+
+
+LBM_STEP_BATCH_NOALLOC_MAX = 1024
+
+
+def lbm_step_batch_noalloc(states, colls, bspecs, n_steps, stream=None):
+    """lbm_step_batch with the segment tables in the library's own device
+    array (no workspace, nothing allocated)."""
+    n = len(states)
+    sp = (ctypes.POINTER(lbm_state) * n)(*[ctypes.pointer(s) for s in states])
+    cp = (ctypes.POINTER(lbm_collision) * n)(*[ctypes.pointer(c) for c in colls])
+    bp = None
+    if bspecs is not None:
+        bp = (ctypes.POINTER(lbm_bspec) * n)(
+            *[ctypes.pointer(b) if b is not None else ctypes.POINTER(lbm_bspec)() for b in bspecs])
+    _call("lbm_step_batch_noalloc", sp, cp, bp, n, int(n_steps), _stream(stream))
 
 
 def lbm_reduce_batch(states, colls, workspace, stream=None, check=True):

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     lib = lbm.load()
     for name in declared_functions():
         assert hasattr(lib, name), name
-    assert lbm.lbm_abi_version() == 5
+    assert lbm.lbm_abi_version() == 6
 
 
 def test_struct_sizes_match_header_layout():
@@ -160,6 +160,19 @@ def test_batch_workspace_checked_on_host():
            workspace_bytes=0)
     expect(lbm.LBM_ENOMEM, lbm.lbm_step_batch, states, [c] * n, None, 1, 0, workspace=16,
            workspace_bytes=need - 1)
+
+
+def test_noalloc_batch_checked_on_host():
+    """The allocation-free batch refuses more states than its device array
+    holds, and mismatched states, before any device work."""
+    n = lbm.LBM_STEP_BATCH_NOALLOC_MAX + 1
+    states = [_fake_state() for _ in range(n)]
+    c = lbm.collision()
+    expect(lbm.LBM_ENOMEM, lbm.lbm_step_batch_noalloc, states, [c] * n, None, 1, 0)
+    assert b"at most 1024" in lbm.load().lbm_last_error()
+    a = _fake_state(storage=lbm.STORE_F32)
+    b = _fake_state(storage=lbm.STORE_F64)
+    expect(lbm.LBM_ESTATE, lbm.lbm_step_batch_noalloc, [a, b], [c, c], None, 1, 0)
 
 
 def test_launch_table_roundtrip():
