@@ -190,8 +190,11 @@ typedef struct {
 } lbm_collision;
 
 /* Boundary classes for labels 2..9.  UBB: moving wall u (bounce-back plus
- * 6 w_i rho_w c_i.u, rho_w = 1); PRESSURE: anti-bounce-back to density rho
- * (-f + 2 w_i rho, the O(u^2) term dropped); NOSLIP: plain bounce-back. */
+ * 6 w_i rho_w c_i.u, rho_w = 1); PRESSURE: anti-bounce-back to density rho,
+ * -f + 2 w_i rho (1 + 9/2 (c_i.u)^2 - 3/2 u.u) with u the fluid cell's
+ * velocity at the current time (its u member is unused); NOSLIP: plain
+ * bounce-back.  The paper specifies the no-slip and velocity rules; the
+ * pressure rule is this library's outlet. */
 typedef struct {
   int32_t type;          /* LBM_BC_*                                           */
   int32_t reserved;

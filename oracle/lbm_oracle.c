@@ -479,15 +479,33 @@ int orc_collide_cells(const orc_params* P, int64_t n, const double* f_in, double
 
 /* ------------------------------------------------------------------ */
 /* Boundary rule for one pulled population (Section "Sparse Boundary    */
-/* Conditions").  `own_opp` is the cell's own post-collision population */
-/* in the opposite direction.  Labels: 0 fluid, 1 solid (halfway        */
-/* bounce-back), 2+c boundary class c.  UBB: moving-wall bounce-back    */
-/* with rho_w = 1; pressure: anti-bounce-back with the O(u^2) term      */
-/* dropped.                                                             */
+/* Conditions" describes no-slip and velocity bounce-back; the pressure */
+/* outlet is this build's reading).  `own_opp` is the cell's own        */
+/* post-collision population in the opposite direction and u the       */
+/* cell's velocity at the same time (orc_cell_velocity; read for        */
+/* pressure only).  Labels: 0 fluid, 1 solid (halfway bounce-back), 2+c */
+/* boundary class c.  UBB: moving-wall bounce-back with rho_w = 1;      */
+/* pressure: anti-bounce-back,                                          */
+/*   f_i = -own_opp + 2 w_i rho_out (1 + 9/2 (c_i.u)^2 - 3/2 u.u),       */
+/* i.e. the sum of the two opposite second-order equilibria at          */
+/* (rho_out, u), so a cell in equilibrium at rho_out gets the           */
+/* equilibrium back.                                                    */
 /* ------------------------------------------------------------------ */
 
+/* rho = sum f*, u = (sum c f* - F/2) / rho of one cell's post-collision
+ * populations (the velocity the moments output reports). */
+static void orc_cell_velocity(const orc_stencil* s, const orc_params* P, const double* fs,
+                              double u[3]) {
+  double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < s->q; ++a) {
+    rho += fs[a];
+    for (int d = 0; d < 3; ++d) j[d] += s->c[a][d] * fs[a];
+  }
+  for (int d = 0; d < 3; ++d) u[d] = (j[d] - 0.5 * P->force[d]) / rho;
+}
+
 static double orc_wall_value(const orc_stencil* s, const orc_params* P, int i, int label,
-                             double own_opp) {
+                             double own_opp, const double u[3]) {
   if (label <= 1) return own_opp;
   int cls = label - 2;
   if (cls >= P->n_classes) return own_opp;
@@ -497,7 +515,11 @@ static double orc_wall_value(const orc_stencil* s, const orc_params* P, int i, i
                 s->c[i][2] * P->cls_u[cls][2];
     return own_opp + 6.0 * s->w[i] * 1.0 * cu;
   }
-  if (type == ORC_BC_PRESSURE) return -own_opp + 2.0 * s->w[i] * P->cls_rho[cls];
+  if (type == ORC_BC_PRESSURE) {
+    double cu = s->c[i][0] * u[0] + s->c[i][1] * u[1] + s->c[i][2] * u[2];
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    return -own_opp + 2.0 * s->w[i] * P->cls_rho[cls] * (1.0 + 4.5 * cu * cu - 1.5 * uu);
+  }
   return own_opp;
 }
 
@@ -541,6 +563,10 @@ int orc_dense_step(const orc_params* P, const uint8_t* labels, int nx, int ny, i
           for (int i = 0; i < q; ++i) B[i * N + lin] = A[i * N + lin];
           continue;
         }
+        /* the cell's own velocity at time t, for pressure outlets */
+        double own[27], u[3];
+        for (int i = 0; i < q; ++i) own[i] = A[i * N + lin];
+        orc_cell_velocity(&s, P, own, u);
         f[0] = A[lin];
         for (int i = 1; i < q; ++i) {
           /* pull: f_i(x) comes from x - c_i */
@@ -550,7 +576,7 @@ int orc_dense_step(const orc_params* P, const uint8_t* labels, int nx, int ny, i
           if (lab == 0)
             f[i] = A[i * N + y_lin];
           else
-            f[i] = orc_wall_value(&s, P, i, lab, A[s.opp[i] * N + lin]);
+            f[i] = orc_wall_value(&s, P, i, lab, A[s.opp[i] * N + lin], u);
         }
         orc_collide(&s, P, f, fs);
         for (int i = 0; i < q; ++i) B[i * N + lin] = fs[i];
@@ -774,15 +800,34 @@ int orc_sparse_build(const uint8_t* labels, int nx, int ny, int nz, uint32_t per
 /* Boundary-link update applied before every AA step: the slot that will be
  * pulled across a boundary link gets the wall rule of orc_wall_value
  * applied to the value it currently holds (the cell's own opposite-direction
- * population, in both parities). */
-static void orc_sparse_links(const orc_stencil* s, const orc_params* P, int64_t n_links,
-                             const int32_t* links, double* pdf) {
+ * population, in both parities).  The velocity of every link's cell is
+ * taken first, from the state before any link of this step is applied
+ * (as the dense scheme reads it from the unmodified previous array): the
+ * cell's post-collision populations sit in its natural slots at even t and
+ * where it pulled the opposite populations from at odd t. */
+static int orc_sparse_links(const orc_stencil* s, const orc_params* P, int64_t n_links,
+                            const int32_t* links, double* pdf, int64_t S,
+                            const int32_t* index, int64_t t) {
+  if (n_links <= 0) return 0;
+  double* uu = (double*)malloc(sizeof(double) * 3 * (size_t)n_links);
+  if (!uu) return -1;
+  for (int64_t l = 0; l < n_links; ++l) {
+    int i = links[2 * l + 1] & 0xff;
+    int64_t k = links[2 * l] - (int64_t)s->opp[i] * S;
+    double fs[27];
+    for (int a = 0; a < s->q; ++a)
+      fs[a] = ((t & 1) == 0 || a == 0) ? pdf[(int64_t)a * S + k]
+                                       : pdf[index[(int64_t)(s->opp[a] - 1) * S + k]];
+    orc_cell_velocity(s, P, fs, uu + 3 * l);
+  }
   for (int64_t l = 0; l < n_links; ++l) {
     int64_t pos = links[2 * l];
     int i = links[2 * l + 1] & 0xff;
     int cls = (links[2 * l + 1] >> 8) & 0xff;
-    pdf[pos] = orc_wall_value(s, P, i, cls + 2, pdf[pos]);
+    pdf[pos] = orc_wall_value(s, P, i, cls + 2, pdf[pos], uu + 3 * l);
   }
+  free(uu);
+  return 0;
 }
 
 /* One AA step (Section "In-place Streaming: AA Pattern").
@@ -796,7 +841,7 @@ int orc_sparse_step(const orc_params* P, int64_t n_fluid, int64_t S, const int32
   if ((P->kind == ORC_CUMULANT || P->kind == ORC_CM) && P->q != 27) return -1;
   if (P->kind == ORC_MRT && P->q != 19) return -1;
   const int q = s.q;
-  orc_sparse_links(&s, P, n_links, links, pdf);
+  if (orc_sparse_links(&s, P, n_links, links, pdf, S, index, t)) return -1;
   if ((t & 1) == 0) {
 #pragma omp parallel for schedule(static) if (n_fluid >= ORC_PAR_MIN)
     for (int64_t k = 0; k < n_fluid; ++k) {

@@ -263,10 +263,16 @@ Seg make_seg(const lbm_state* s, const lbm_collision* c) {
   return g;
 }
 
-lbm_status link_update(const lbm_state* s, const lbm_bspec* bs, hipStream_t st) {
+// Boundary links of one state before a step.  natural: the populations sit
+// in their natural slots (AA at even t, every pull step); the pressure rule
+// reads the cell's velocity from them (coll supplies the force).
+lbm_status link_update(const lbm_state* s, const lbm_collision* c, const lbm_bspec* bs,
+                       bool natural, hipStream_t st) {
   if (s->layout.n_links == 0) return LBM_OK;
   LinkArgs la;
   memset(&la, 0, sizeof(la));
+  la.g = make_seg(s, c);
+  la.natural = natural ? 1 : 0;
   la.pdf = s->pdf;
   la.links = s->links;
   la.n_links = (uint32_t)s->layout.n_links;
@@ -606,7 +612,8 @@ static lbm_status step_group(lbm_state* const* states, const lbm_collision* cons
     const bool odd = (states[0]->t & 1) == 0;
     const lbm_launch& cfg = odd ? cfg_odd : cfg_even;
     for (int32_t j = 0; j < n; ++j) {
-      lbm_status rc = link_update(states[j], bspecs ? bspecs[j] : nullptr, st);
+      lbm_status rc = link_update(states[j], colls[j], bspecs ? bspecs[j] : nullptr,
+                                  (states[j]->t & 1) == 0, st);
       if (rc) return rc;
     }
     for (const LaunchGroup& gr : odd ? odd_groups : even_groups) {
@@ -663,7 +670,7 @@ lbm_status lbm_step_pull(lbm_state* s, void** spare, int32_t n_steps, const lbm_
     return fail(LBM_EINVAL, "pull steps need the int32 index-list");
   const int idx = s->index16 ? IDX_16 : IDX_I32;
   for (int32_t step = 0; step < n_steps; ++step) {
-    rc = link_update(s, bs, st);
+    rc = link_update(s, c, bs, true, st);
     if (rc) return rc;
     if (s->layout.n_fluid > 0) {
       StepArgs a;

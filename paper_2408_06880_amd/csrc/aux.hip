@@ -75,86 +75,14 @@ hipError_t launch_init(int q, int storage, void* pdf, uint32_t S, uint32_t nf, d
   return hipErrorInvalidValue;
 }
 
-// ------------------------------------------------------------- links
-// Boundary link update, applied before every step to the slot that the
-// link's cell pulls across the boundary (Section "Sparse Boundary
-// Conditions", realised as an affine update of that slot instead of
-// appended boundary PDFs), in deviation form:
-//   UBB:      d <- d + 6 w_i (c_i . u_w)               (rho_w = 1)
-//   pressure: d <- -d + 2 w_i (rho_out - 1)
-template <int Q, int ST>
-__global__ __launch_bounds__(256) void k_links(const LinkArgs a) {
-  using SP = Store<ST>;
-  using T = typename SP::T;
-  using R = typename SP::R;
-  const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= a.n_links) return;
-  const uint32_t pos = (uint32_t)a.links[2 * l];
-  const int meta = a.links[2 * l + 1];
-  const int i = meta & 0xff, cls = (meta >> 8) & 0xff;
-  int type = 0;
-  double ux = 0, uy = 0, uz = 0, rho = 1.0;
-#pragma unroll
-  for (int c = 0; c < 8; ++c)
-    if (c == cls && c < a.n_classes) {
-      type = a.type[c];
-      ux = a.u[c][0];
-      uy = a.u[c][1];
-      uz = a.u[c][2];
-      rho = a.rho[c];
-    }
-  if (type == 0) return;
-  int cx, cy, cz;
-  double w;
-  dir_of<Q>(i, cx, cy, cz, w);
-  T* pdf = static_cast<T*>(a.pdf);
-  R dv = SP::load(pdf[pos], R(w), R(a.inv_scale));
-  if (type == 1)
-    dv = dv + R(6.0 * w * (cx * ux + cy * uy + cz * uz));
-  else
-    dv = -dv + R(2.0 * w * (rho - 1.0));
-  pdf[pos] = SP::store(dv, R(w), R(a.scale));
-}
-
-template <int Q>
-static hipError_t launch_links_q(int storage, const LinkArgs& a, hipStream_t st) {
-  dim3 g((a.n_links + 255) / 256), b(256);
-  switch (storage) {
-    case ST_F64: hipLaunchKernelGGL((k_links<Q, ST_F64>), g, b, 0, st, a); break;
-    case ST_F32: hipLaunchKernelGGL((k_links<Q, ST_F32>), g, b, 0, st, a); break;
-    case ST_F16DEV: hipLaunchKernelGGL((k_links<Q, ST_F16DEV>), g, b, 0, st, a); break;
-    case ST_BF16DEV: hipLaunchKernelGGL((k_links<Q, ST_BF16DEV>), g, b, 0, st, a); break;
-    case ST_F32DEV: hipLaunchKernelGGL((k_links<Q, ST_F32DEV>), g, b, 0, st, a); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_links(int storage, const LinkArgs& a, hipStream_t st) {
-  if (a.n_links == 0) return hipSuccess;
-  if (a.q == 19) return launch_links_q<19>(storage, a, st);
-  if (a.q == 27) return launch_links_q<27>(storage, a, st);
-  return hipErrorInvalidValue;
-}
-
 // ----------------------------------------------------------- moments
-// Pull position of population i of cell k from the run-compressed
-// index-list, decoded by one thread alone: the value of the run holding
-// lane k % 64 (lane 0 always starts a run) plus the lane.  The step kernel
-// decodes runs a whole wave at a time instead.
-__device__ __forceinline__ uint32_t run_pos(const Seg& g, int q, int i, uint32_t k) {
-  const uint32_t w = k / kRunWave, lane = k % kRunWave;
-  const LBM_GLOBAL uint64_t* mk = gp(g.rmask) + (size_t)w * (q - 1);
-  uint32_t vb = gp(g.rvoff)[w];
-  for (int d = 1; d < i; ++d) vb += (uint32_t)__popcll(mk[d - 1]);
-  const uint64_t upto = lane == kRunWave - 1 ? ~0ull : ((2ull << lane) - 1ull);
-  const uint32_t r = (uint32_t)__popcll(mk[i - 1] & upto) - 1u;
-  return (uint32_t)gp(g.rval)[vb + r] + lane;
-}
-
 // Post-collision deviations of cell k at the current time in natural order.
-// Even t: natural slots.  Odd t: population j sits where the cell pulled
-// population opp(j) from in the last (odd) step.
+// Even t: natural slots.  Odd t: population opp(i) sits where the cell
+// pulled population i from in the last (odd) step.  The run form is decoded
+// by this thread alone, directions in storage order: the pull position of
+// direction i is the value of the run holding lane k % 64 (the count of run
+// starts in lanes 0..lane, minus one, after the runs of directions 1..i-1)
+// plus the lane.  (The step kernels decode runs a whole wave at a time.)
 template <int Q, int ST, bool ODD_T>
 __device__ __forceinline__ void gather_post(const Seg& g, uint32_t k,
                                             typename Store<ST>::R (&d)[Q]) {
@@ -163,18 +91,153 @@ __device__ __forceinline__ void gather_post(const Seg& g, uint32_t k,
   using R = typename SP::R;
   const LBM_GLOBAL T* pdf = gp(static_cast<const T*>(g.pdf));
   const R isc = R(g.inv_scale);
-  const uint32_t t16 = k / kTile16;
+  uint32_t pos[Q];
 #pragma unroll
-  for (int j = 0; j < Q; ++j) {
-    uint32_t pos;
-    if (ODD_T && j > 0)
-      pos = g.rval    ? run_pos(g, Q, opp(j), k)
-            : g.off16 ? pos16(g, Q, opp(j), j, k, t16)
-                      : (uint32_t)gp(g.idx)[(size_t)(opp(j) - 1) * g.S + k];
-    else
-      pos = (uint32_t)j * g.S + k;
-    d[j] = SP::load(pdf[pos], R(Lattice<Q>::w(j)), isc);
+  for (int j = 0; j < Q; ++j) pos[j] = (uint32_t)j * g.S + k;
+  if (ODD_T) {
+    if (g.rval) {
+      const uint32_t w = k / kRunWave, lane = k % kRunWave;
+      const LBM_GLOBAL uint64_t* mk = gp(g.rmask) + (size_t)w * (Q - 1);
+      const LBM_GLOBAL int32_t* val = gp(g.rval) + gp(g.rvoff)[w];
+      const uint64_t upto = lane == kRunWave - 1 ? ~0ull : ((2ull << lane) - 1ull);
+      uint32_t vb = 0;
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        const uint64_t m = mk[i - 1];
+        const uint32_t r = (uint32_t)__popcll(m & upto) - 1u;
+        pos[opp(i)] = (uint32_t)val[vb + r] + lane;
+        vb += (uint32_t)__popcll(m);
+      }
+    } else {
+      const uint32_t t16 = k / kTile16;
+#pragma unroll
+      for (int j = 1; j < Q; ++j)
+        pos[j] = g.off16 ? pos16(g, Q, opp(j), j, k, t16)
+                         : (uint32_t)gp(g.idx)[(size_t)(opp(j) - 1) * g.S + k];
+    }
   }
+#pragma unroll
+  for (int j = 0; j < Q; ++j) d[j] = SP::load(pdf[pos[j]], R(Lattice<Q>::w(j)), isc);
+}
+
+// ------------------------------------------------------------- links
+// Boundary link update, applied before every step to the slot that the
+// link's cell pulls across the boundary (Section "Sparse Boundary
+// Conditions", realised as an update of that slot instead of appended
+// boundary PDFs), in deviation form:
+//   UBB:      d <- d + 6 w_i (c_i . u_w)               (rho_w = 1)
+//   pressure: d <- -d + 2 w_i (rho_out (1 + 9/2 (c_i.u)^2 - 3/2 u.u) - 1)
+// with u the cell's velocity at the current time (anti-bounce-back: the
+// sum of the two opposite second-order equilibria at (rho_out, u)).  The
+// links are ordered by cell, so the first link of each cell updates all of
+// that cell's links: it reads the velocity from the cell's populations
+// before any of their slots changes, and no two threads touch one cell's
+// slots.  A link slot holds a population of its own cell at both parities,
+// so cells never touch each other's slots.
+// Fluid cell of link l (its slot is opp(i) * S + k).
+__device__ __forceinline__ uint32_t link_cell(const LinkArgs& a, uint32_t l) {
+  const int i = a.links[2 * l + 1] & 0xff;
+  return (uint32_t)a.links[2 * l] - (uint32_t)opp(i) * a.g.S;
+}
+
+template <int Q, int ST, bool ODD_T>
+__global__ __launch_bounds__(256) void k_links(const LinkArgs a) {
+  using SP = Store<ST>;
+  using T = typename SP::T;
+  using R = typename SP::R;
+  const uint32_t l0 = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l0 >= a.n_links) return;
+  const uint32_t k = link_cell(a, l0);
+  if (l0 > 0 && link_cell(a, l0 - 1) == k) return;  // not the cell's first link
+  // The cell's links are l0, l0 + 1, ... (at most Q - 1 of them; links are
+  // ordered by cell).  All metadata and slot values are loaded before any
+  // slot is written, so the loads overlap instead of waiting one by one.
+  T* pdf = static_cast<T*>(a.pdf);
+  uint32_t pos[Q - 1];
+  int meta[Q - 1];
+  T v[Q - 1];
+  bool on[Q - 1];
+  bool pressure = false;
+#pragma unroll
+  for (int m = 0; m < Q - 1; ++m) {
+    const uint32_t l = l0 + (uint32_t)m;
+    on[m] = l < a.n_links && link_cell(a, l) == k;
+    pos[m] = 0;
+    meta[m] = 0;
+    if (on[m]) {
+      pos[m] = (uint32_t)a.links[2 * l];
+      meta[m] = a.links[2 * l + 1];
+      const int cls = (meta[m] >> 8) & 0xff;
+      pressure = pressure || (cls < a.n_classes && a.type[cls] == 2);
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < Q - 1; ++m)
+    if (on[m]) v[m] = pdf[pos[m]];
+  R ux = 0, uy = 0, uz = 0;
+  if (pressure) {
+    R d[Q];
+    gather_post<Q, ST, ODD_T>(a.g, k, d);
+    R drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      drho += d[j];
+      jx += R(Lattice<Q>::cx[j]) * d[j];
+      jy += R(Lattice<Q>::cy[j]) * d[j];
+      jz += R(Lattice<Q>::cz[j]) * d[j];
+    }
+    const R r = R(1) + drho;
+    ux = (jx - R(0.5) * R(a.g.F[0])) / r;
+    uy = (jy - R(0.5) * R(a.g.F[1])) / r;
+    uz = (jz - R(0.5) * R(a.g.F[2])) / r;
+  }
+#pragma unroll
+  for (int m = 0; m < Q - 1; ++m) {
+    if (!on[m]) continue;
+    const int i = meta[m] & 0xff, cls = (meta[m] >> 8) & 0xff;
+    const int type = cls < a.n_classes ? a.type[cls] : 0;
+    if (type == 0) continue;
+    int cx, cy, cz;
+    double w;
+    dir_of<Q>(i, cx, cy, cz, w);
+    R dv = SP::load(v[m], R(w), R(a.inv_scale));
+    if (type == 1) {
+      dv = dv + R(6.0 * w * (cx * a.u[cls][0] + cy * a.u[cls][1] + cz * a.u[cls][2]));
+    } else {
+      const R cu = R(cx) * ux + R(cy) * uy + R(cz) * uz;
+      const R uu = ux * ux + uy * uy + uz * uz;
+      dv = -dv + R(2.0 * w * (a.rho[cls] - 1.0)) +
+           R(2.0 * w * a.rho[cls]) * (R(4.5) * cu * cu - R(1.5) * uu);
+    }
+    pdf[pos[m]] = SP::store(dv, R(w), R(a.scale));
+  }
+}
+
+template <int Q, bool ODD_T>
+static hipError_t launch_links_qt(int storage, const LinkArgs& a, hipStream_t st) {
+  dim3 g((a.n_links + 255) / 256), b(256);
+  switch (storage) {
+    case ST_F64: hipLaunchKernelGGL((k_links<Q, ST_F64, ODD_T>), g, b, 0, st, a); break;
+    case ST_F32: hipLaunchKernelGGL((k_links<Q, ST_F32, ODD_T>), g, b, 0, st, a); break;
+    case ST_F16DEV: hipLaunchKernelGGL((k_links<Q, ST_F16DEV, ODD_T>), g, b, 0, st, a); break;
+    case ST_BF16DEV: hipLaunchKernelGGL((k_links<Q, ST_BF16DEV, ODD_T>), g, b, 0, st, a); break;
+    case ST_F32DEV: hipLaunchKernelGGL((k_links<Q, ST_F32DEV, ODD_T>), g, b, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int Q>
+static hipError_t launch_links_q(int storage, const LinkArgs& a, hipStream_t st) {
+  return a.natural ? launch_links_qt<Q, false>(storage, a, st)
+                   : launch_links_qt<Q, true>(storage, a, st);
+}
+
+hipError_t launch_links(int storage, const LinkArgs& a, hipStream_t st) {
+  if (a.n_links == 0) return hipSuccess;
+  if (a.q == 19) return launch_links_q<19>(storage, a, st);
+  if (a.q == 27) return launch_links_q<27>(storage, a, st);
+  return hipErrorInvalidValue;
 }
 
 template <int Q, int ST, bool ODD_T, class O>

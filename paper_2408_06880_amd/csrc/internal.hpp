@@ -18,16 +18,21 @@ hipError_t launch_aa_q27(int coll, int storage, int mode, int idx, const StepArg
 
 // Boundary-class coefficients of one solve, precomputed on the host:
 // for class c, type[c] in {0 noslip, 1 UBB, 2 pressure}; u[c][3]; rho[c].
+// g describes the solve (buffers, index forms, force, 16-bit scale) for the
+// gather of a cell's velocity; natural = 1 when the populations sit in
+// their natural slots (even t of the AA pattern, every pull step).
 struct LinkArgs {
   void* pdf;
   const int32_t* links;
   uint32_t n_links;
   int32_t q;
   int32_t n_classes;
+  int32_t natural;
   int32_t type[8];
   double u[8][3];
   double rho[8];
   float scale, inv_scale;
+  Seg g;
 };
 
 // aux.hip

@@ -199,8 +199,10 @@ def random_mask(shape, solid_fraction, seed, n_classes=0, class_fraction=0.0):
     return lab
 
 
-def _capsule_stamp(mask, value, p0, p1, r, only_where=None):
-    """Set voxels within distance r of segment p0-p1 (non-periodic box)."""
+def _capsule_stamp(mask, value, p0, p1, r, only_where=None, flat_end=False, flat_start=False):
+    """Set voxels within distance r of segment p0-p1 (non-periodic box).
+    flat_end / flat_start: cut the tube by the plane through p1 / p0
+    normal to the axis instead of rounding it (a cylinder end)."""
     nz, ny, nx = mask.shape
     lo = np.floor(np.minimum(p0, p1) - r).astype(int)
     hi = np.ceil(np.maximum(p0, p1) + r).astype(int)
@@ -215,9 +217,14 @@ def _capsule_stamp(mask, value, p0, p1, r, only_where=None):
     P = np.stack([X, Y, Z], axis=-1).astype(np.float64)
     d = p1 - p0
     dd = float(d @ d)
-    t = np.clip(((P - p0) @ d) / dd, 0.0, 1.0) if dd > 0 else np.zeros(P.shape[:-1])
+    tr = ((P - p0) @ d) / dd if dd > 0 else np.zeros(P.shape[:-1])
+    t = np.clip(tr, 0.0, 1.0)
     Q = p0 + t[..., None] * d
     inside = np.sum((P - Q) ** 2, axis=-1) <= r * r
+    if flat_end:
+        inside &= tr <= 1.0
+    if flat_start:
+        inside &= tr > 0.0
     sub = mask[zs[0]:zs[-1] + 1, ys[0]:ys[-1] + 1, xs[0]:xs[-1] + 1]
     if only_where is not None:
         inside &= sub == only_where
@@ -236,9 +243,12 @@ def vessel_tree(n=512, r0=24.0, ratio=0.79, k_len=6.0, seed=7, angle_deg=(20.0, 
     segments stay inside the box margin (r + 2 cells); if only one daughter
     fits any candidate it grows alone.  A branch ends (outlet) when the
     daughter radius would drop below r_min or no daughter fits.  Tubes are
-    capsules (their union is the lumen).  Labels: fluid 0, tissue 1, inlet
-    class 0 (label 2) = the z = 0 disk, outlet class 1 (label 3) = a one-cell
-    cap just past each terminal end (on tissue only).
+    capsules (their union is the lumen), except that a terminal segment ends
+    flat (cut by the plane normal to its axis through its end point).
+    Labels: fluid 0, tissue 1, inlet class 0 (label 2) = the z = 0 disk,
+    outlet class 1 (label 3) = the tissue cells of the slab just past each
+    flat end (axial distance in (0, 2], radial distance <= r), so that every
+    fluid cell of the end face has its axial neighbours in the outlet.
     Returns (labels, periodic=0, info)."""
     rng = np.random.default_rng(seed)
     mask = np.ones((n, n, n), np.uint8)  # tissue everywhere
@@ -252,9 +262,10 @@ def vessel_tree(n=512, r0=24.0, ratio=0.79, k_len=6.0, seed=7, angle_deg=(20.0, 
     while stack:
         p0, axis, r, depth = stack.pop()
         p1 = p0 + axis * k_len * r
-        segs.append((p0, p1, r))
+        segs.append([p0, p1, r, False])
         rd = ratio * r
         if rd < r_min or depth >= max_depth:
+            segs[-1][3] = True
             ends.append((p1, axis, r))
             continue
         tmp = np.array([1.0, 0.0, 0.0]) if abs(axis[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
@@ -277,16 +288,17 @@ def vessel_tree(n=512, r0=24.0, ratio=0.79, k_len=6.0, seed=7, angle_deg=(20.0, 
             if best is None and any(fits):
                 best = [d for d, f in zip(dirs, fits) if f]
         if not best:
+            segs[-1][3] = True
             ends.append((p1, axis, r))
             continue
         for d in best:
             stack.append((p1.copy(), d, rd, depth + 1))
-    for p0, p1, r in segs:
-        _capsule_stamp(mask, 0, p0, p1, r)
-    # outlet caps: one-cell-thick disc just past each terminal end, only on tissue
+    for p0, p1, r, terminal in segs:
+        _capsule_stamp(mask, 0, p0, p1, r, flat_end=terminal)
+    # outlets: the slab just past each flat end, on tissue only
     for p1, axis, r in ends:
-        c = p1 + axis * (r + 1.0)
-        _capsule_stamp(mask, 3, c, c + axis * 0.5, r, only_where=1)
+        _capsule_stamp(mask, 3, p1, p1 + axis * 2.0, r, only_where=1, flat_end=True,
+                       flat_start=True)
     # inlet: the z = 0 layer inside the root disk becomes the inlet class
     yy, xx = np.mgrid[0:n, 0:n]
     disk = (xx - n / 2.0) ** 2 + (yy - n / 2.0) ** 2 <= r0 * r0

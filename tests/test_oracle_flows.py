@@ -209,6 +209,33 @@ def test_couette_moving_wall(kind, tau):
     assert np.max(np.abs(rho[0, 1:, 0] - 1.0)) < 1e-10
 
 
+def test_pressure_outlet_returns_equilibrium_with_velocity():
+    """Anti-bounce-back at a pressure outlet returns the sum of the two
+    opposite second-order equilibria at (rho_out, u): a cell in equilibrium
+    at rho_out moving with u gets exactly the equilibrium population back
+    through the outlet, O(u^2) term included (pure streaming, no collision,
+    so the pulled values are the boundary rule's output)."""
+    lab = np.zeros((1, 1, 3), np.uint8)
+    lab[0, 0, 2] = 2                      # x = 2: pressure outlet; periodic in y and z
+    rho_out, u0 = 1.003, (0.05, 0.02, -0.01)
+    p = oracle.params(q=19, kind=oracle.NONE,
+                      classes=[(oracle.BC_PRESSURE, (0, 0, 0), rho_out)])
+    rho = np.full((1, 1, 3), rho_out)
+    u = np.zeros((3, 1, 1, 3))
+    for a in range(3):
+        u[a] = u0[a]
+    A = _feq_field(19, rho, u)
+    B = oracle.dense_run(p, lab, 6, 1, A)
+    c, _, _ = oracle.stencil(19)
+    from_outlet = [i for i in range(1, 19) if c[i, 0] == -1]   # pulled from x + 1 = outlet
+    assert len(from_outlet) == 5
+    for i in from_outlet:
+        assert abs(B[i, 0, 0, 1] - A[i, 0, 0, 1]) <= 1e-14 * A[i, 0, 0, 1]
+    # without the velocity terms the returned value would be off by
+    # 2 w rho (9/2 (c.u)^2 - 3/2 u.u), far above rounding
+    assert abs(4.5 * 0.05 ** 2 - 1.5 * (0.05 ** 2 + 0.02 ** 2 + 0.01 ** 2)) > 1e-4
+
+
 def test_pressure_outlet_sets_density():
     """Closed box with one pressure-outlet face and no force: the fluid
     relaxes to rest at the outlet density (anti-bounce-back rule)."""
