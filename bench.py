@@ -529,9 +529,6 @@ def main():
     ap.add_argument("--even-cells", type=int, default=0, choices=[0, 1, 2],
                     help="cells per thread of the even-step kernel (0: the library's "
                          "default, two for 16-bit storage)")
-    ap.add_argument("--odd-cells", type=int, default=0, choices=[0, 1, 2],
-                    help="cells per thread of the odd-step kernel (run form; 0: the "
-                         "library's default)")
     ap.add_argument("--tune", action="store_true",
                     help="run the launch tuner on this solve first (untimed) and keep the "
                          "fastest configurations")
@@ -775,11 +772,10 @@ def packing_record(lbm, torch, costmodel, lab_dev, per, q, order, args, name, co
     if args.pipelined:
         b, x = lbm.lbm_get_launch(lbm.KERNEL_ODD, q, storage)
         lbm.lbm_set_launch(lbm.KERNEL_ODD, q, storage, 256, x, 1)
-    for kern, cells in ((lbm.KERNEL_EVEN, args.even_cells), (lbm.KERNEL_ODD, args.odd_cells)):
-        if cells:
-            cfg = list(lbm.lbm_get_launch(kern, q, storage, full=True))
-            cfg[3] = cells
-            lbm.lbm_set_launch(kern, q, storage, *cfg)
+    if args.even_cells:
+        cfg = list(lbm.lbm_get_launch(lbm.KERNEL_EVEN, q, storage, full=True))
+        cfg[3] = args.even_cells
+        lbm.lbm_set_launch(lbm.KERNEL_EVEN, q, storage, *cfg)
     for kern, blk, g in ((lbm.KERNEL_ODD, args.odd_block, args.odd_groups),
                          (lbm.KERNEL_EVEN, args.even_block, args.even_groups)):
         cfg = list(lbm.lbm_get_launch(kern, q, storage, full=True))

@@ -422,11 +422,8 @@ typedef struct {
   int32_t cells_per_thread; /* even kernel: 2 = two neighbouring cells per    */
                       /* thread with 2-wide loads/stores, used when every      */
                       /* state of the launch has an even stride (one cell      */
-                      /* otherwise).  Odd kernel: 2 = two neighbouring cells   */
-                      /* per thread for states read through the run form      */
-                      /* (2-wide gathers and scatters where both cells lie in  */
-                      /* one run; other forms take one cell).  0 or 1 = one   */
-                      /* cell; dense and pipelined launches take one cell.    */
+                      /* otherwise); 0 or 1 = one cell (the only choice for    */
+                      /* the other kernels)                                    */
   int32_t max_groups_per_cu; /* odd and even AA kernels: 0 = as many resident */
                       /* workgroups per CU as registers allow; n in [2, 16] =  */
                       /* at most n (dynamic LDS is reserved for the purpose;   */

@@ -320,9 +320,8 @@ lbm_status lbm_set_launch(int32_t kernel, int32_t q, int32_t storage, const lbm_
   if (cfg->pipelined != 0 && (cfg->pipelined != 1 || kernel != LBM_KERNEL_ODD || cfg->block != 256))
     return fail(LBM_EINVAL, "pipelined applies to the odd kernel with block 256 only");
   if (cfg->cells_per_thread < 0 || cfg->cells_per_thread > 2 ||
-      (cfg->cells_per_thread == 2 && (kernel == LBM_KERNEL_DENSE || cfg->pipelined)))
-    return fail(LBM_EINVAL,
-                "cells_per_thread must be 0, 1, or 2 for the odd and even kernels (got %d)",
+      (cfg->cells_per_thread == 2 && kernel != LBM_KERNEL_EVEN))
+    return fail(LBM_EINVAL, "cells_per_thread must be 0, 1, or 2 for the even kernel (got %d)",
                 cfg->cells_per_thread);
   if (cfg->max_groups_per_cu != 0 &&
       (cfg->max_groups_per_cu < 2 || cfg->max_groups_per_cu > 16 ||
@@ -570,19 +569,15 @@ static lbm_status step_group(lbm_state* const* states, const lbm_collision* cons
   segs.reserve(2 * (size_t)n);
   std::vector<LaunchGroup> odd_groups, even_groups;
   // Odd steps run one launch per index form, each form being a kernel of
-  // its own; even steps never read indices.  Two cells per thread in the
-  // odd step exist for the run form only.
+  // its own; even steps never read indices.
   for (int form = IDX_I32; form <= IDX_RUN; ++form) {
-    const bool pair = form == IDX_RUN && cfg_odd.cells_per_thread == 2;
-    LaunchGroup gr{pair                                          ? MODE_ODD2
-                   : form == IDX_16 && cfg_odd.pipelined == 1 ? MODE_ODD_PIPE
-                                                              : MODE_ODD,
-                   form, (uint32_t)segs.size(), 0, 0};
+    LaunchGroup gr{form == IDX_16 && cfg_odd.pipelined == 1 ? MODE_ODD_PIPE : MODE_ODD, form,
+                   (uint32_t)segs.size(), 0, 0};
     for (int32_t j = 0; j < n; ++j) {
       if (states[j]->layout.n_fluid == 0 || index_form(states[j]) != form) continue;
       Seg g = make_seg(states[j], colls[j]);
       g.tile0 = gr.ntiles;
-      gr.ntiles += ceil_div(g.nf, (uint64_t)cfg_odd.block * (pair ? 2 : 1));
+      gr.ntiles += ceil_div(g.nf, (uint64_t)cfg_odd.block);
       segs.push_back(g);
       gr.nseg += 1;
     }
@@ -617,10 +612,6 @@ static lbm_status step_group(lbm_state* const* states, const lbm_collision* cons
       if (rc) return rc;
     }
     for (const LaunchGroup& gr : odd ? odd_groups : even_groups) {
-      // a residency cap chosen for the two-cell odd kernel does not carry
-      // over to the one-cell kernel of the other index forms
-      lbm_launch gcfg = cfg;
-      if (odd && cfg.cells_per_thread == 2 && gr.mode != MODE_ODD2) gcfg.max_groups_per_cu = 0;
       StepArgs a;
       memset(&a, 0, sizeof(a));
       a.xcd_remap = cfg.xcd_remap;
@@ -630,7 +621,7 @@ static lbm_status step_group(lbm_state* const* states, const lbm_collision* cons
         a.seg0 = segs[gr.first];
       else
         a.segs = table + gr.first;
-      HIP_TRY(launch_aa(q, kind, storage, gr.mode, gr.form, a, gcfg, st), "AA step");
+      HIP_TRY(launch_aa(q, kind, storage, gr.mode, gr.form, a, cfg, st), "AA step");
     }
     for (int32_t j = 0; j < n; ++j) states[j]->t += 1;
   }

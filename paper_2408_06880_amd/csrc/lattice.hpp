@@ -119,11 +119,8 @@ constexpr uint16_t kEscape16 = 0xFFFEu;  // read the int32 index-list
 constexpr uint32_t kMaxOff16 = 0xFFFDu;  // largest stored offset
 
 // Step kernels: even, odd, two-array pull, pipelined odd (compact
-// index-list), even and odd with two cells per thread.
-enum StepMode {
-  MODE_EVEN = 0, MODE_ODD = 1, MODE_PULL = 2, MODE_ODD_PIPE = 3, MODE_EVEN2 = 4,
-  MODE_ODD2 = 5  // odd step, two neighbouring cells per thread (run form)
-};
+// index-list), even with two cells per thread.
+enum StepMode { MODE_EVEN = 0, MODE_ODD = 1, MODE_PULL = 2, MODE_ODD_PIPE = 3, MODE_EVEN2 = 4 };
 
 // Index-list forms read by the odd step.
 enum IndexForm { IDX_I32 = 0, IDX_16 = 1, IDX_RUN = 2 };

@@ -248,123 +248,6 @@ __global__ __launch_bounds__(256) void k_even_pair(const StepArgs a) {
   with_seg(a, tile, [&](const Seg& g) { even_pair_cells<Q, COLL, ST>(g, tile); });
 }
 
-// Two neighbouring elements of one direction block as one access of twice
-// the width.  The address need only be aligned to one element: gfx950 runs
-// with unaligned global access enabled, and the compiler emits a single
-// 2-wide load or store for an element-aligned memcpy.
-template <class T>
-__device__ __forceinline__ void ld_pair(const LBM_GLOBAL T* p, T& a, T& b) {
-  typedef T V __attribute__((ext_vector_type(2)));
-  V v;
-  __builtin_memcpy(&v, (const T*)p, sizeof(V));
-  a = v.x;
-  b = v.y;
-}
-template <class T>
-__device__ __forceinline__ void st_pair(LBM_GLOBAL T* p, T a, T b) {
-  typedef T V __attribute__((ext_vector_type(2)));
-  V v;
-  v.x = a;
-  v.y = b;
-  __builtin_memcpy((T*)p, &v, sizeof(V));
-}
-
-// Odd step, two neighbouring cells per thread, run-compressed index-list.
-// Lane l of a wave updates cells k0 = base + 2l and k1 = k0 + 1 (a wave
-// covers two 64-position groups of the run form: lanes 0-31 the first,
-// 32-63 the second).  Where k1 continues k0's run in direction i, its pull
-// position is k0's plus one, so both populations move as one 2-wide gather
-// and one 2-wide scatter: half the memory instructions of the one-cell
-// kernel, each touching one more cache piece at most instead of one more
-// per 64 elements.  Where a run starts at k1 (or k1 is past the last fluid
-// cell) the two cells take single-element accesses.  Same arithmetic as the
-// one-cell kernel, so the results are bitwise identical.
-template <int Q, int COLL, int ST>
-__device__ __forceinline__ void odd_pair_cells(const Seg& g, uint32_t tile) {
-  using SP = Store<ST>;
-  using T = typename SP::T;
-  using R = typename SP::R;
-  const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t k0 = 2 * ((tile - g.tile0) * blockDim.x + threadIdx.x);
-  const uint32_t nf = g.nf, S = g.S;
-  // run groups of this wave: rw0 (lanes 0-31) and rw0 + 1 (lanes 32-63)
-  const uint32_t kb = __builtin_amdgcn_readfirstlane(k0 - 2 * lane);
-  if (k0 >= nf) return;
-  const uint32_t rw0 = kb / kRunWave;
-  const bool has_hi = kb + kRunWave < S;  // wave-uniform: the second group exists
-  const bool hi = lane >= 32u;
-  const uint32_t j0 = (2u * lane) & 63u;  // position of k0 inside its group
-  const bool k1_ok = k0 + 1 < nf;
-  const LBM_GLOBAL uint64_t* __restrict__ mk0 = gp(g.rmask) + (size_t)rw0 * (Q - 1);
-  const LBM_GLOBAL uint64_t* __restrict__ mk1 = mk0 + (Q - 1);
-  const LBM_GLOBAL int32_t* __restrict__ val = gp(g.rval);
-  const uint32_t vo0 = gp(g.rvoff)[rw0];
-  const uint32_t vo1 = gp(g.rvoff)[rw0 + 1];  // voff has one entry per group plus one
-  // lanes 0..j0 of the group: the run holding j0 is run number
-  // popcount(starts in 0..j0) - 1
-  const uint64_t upto = (2ull << j0) - 1ull;
-  LBM_GLOBAL T* __restrict__ pdf = gp(static_cast<T*>(g.pdf));
-  const R sc = R(g.scale), isc = R(g.inv_scale);
-  uint32_t pos0[Q], pos1[Q];
-  uint32_t split = 0;  // bit i: the two cells take single accesses in direction i
-  pos0[0] = k0;
-  pos1[0] = k0 + 1;
-  if (!k1_ok) split |= 1u;
-  uint32_t vb0 = vo0, vb1 = vo1;
-#pragma unroll
-  for (int i = 1; i < Q; ++i) {
-    const uint64_t m0 = mk0[i - 1];
-    const uint64_t m1 = has_hi ? mk1[i - 1] : 0ull;
-    const uint64_t m = hi ? m1 : m0;
-    const uint32_t vb = hi ? vb1 : vb0;
-    const uint32_t r = (uint32_t)__builtin_popcountll(m & upto) - 1u;
-    pos0[i] = (uint32_t)val[vb + r] + j0;
-    const bool starts = ((m >> (j0 + 1)) & 1ull) != 0;
-    pos1[i] = pos0[i] + 1u;
-    if (starts && k1_ok) pos1[i] = (uint32_t)val[vb + r + 1] + j0 + 1u;
-    if (starts || !k1_ok) split |= 1u << i;
-    vb0 += (uint32_t)__builtin_popcountll(m0);
-    vb1 += (uint32_t)__builtin_popcountll(m1);
-  }
-  T a[Q], b[Q];
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    if (!((split >> i) & 1u)) {
-      ld_pair(pdf + pos0[i], a[i], b[i]);
-    } else {
-      a[i] = ld<LBM_NT_GATHER>(pdf + pos0[i]);
-      b[i] = k1_ok ? ld<LBM_NT_GATHER>(pdf + pos1[i]) : a[i];
-    }
-  }
-  const CollParams<R> p = seg_params<R>(g);
-  R d[Q];
-#pragma unroll
-  for (int i = 0; i < Q; ++i) d[i] = SP::load(a[i], R(Lattice<Q>::w(i)), isc);
-  collide<Q, COLL, R>(d, p);
-#pragma unroll
-  for (int i = 0; i < Q; ++i) a[i] = SP::store(d[opp(i)], R(Lattice<Q>::w(i)), sc);
-#pragma unroll
-  for (int i = 0; i < Q; ++i) d[i] = SP::load(b[i], R(Lattice<Q>::w(i)), isc);
-  collide<Q, COLL, R>(d, p);
-#pragma unroll
-  for (int i = 0; i < Q; ++i) b[i] = SP::store(d[opp(i)], R(Lattice<Q>::w(i)), sc);
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    if (!((split >> i) & 1u)) {
-      st_pair(pdf + pos0[i], a[i], b[i]);
-    } else {
-      st<LBM_NT_SCATTER>(a[i], pdf + pos0[i]);
-      if (k1_ok) st<LBM_NT_SCATTER>(b[i], pdf + pos1[i]);
-    }
-  }
-}
-
-template <int Q, int COLL, int ST>
-__global__ __launch_bounds__(256) void k_odd_pair(const StepArgs a) {
-  const uint32_t tile = a.xcd_remap ? xcd_tile(blockIdx.x, a.ntiles) : blockIdx.x;
-  with_seg(a, tile, [&](const Seg& g) { odd_pair_cells<Q, COLL, ST>(g, tile); });
-}
-
 // Persistent, software-pipelined odd step (compact index-list).  Each
 // workgroup walks tiles v, v + G, v + 2G, ... (G = grid size, a multiple of
 // 8 so that every tile of a workgroup maps to the same XCD range); the
@@ -473,10 +356,6 @@ inline hipError_t launch_aa_cs(int mode, int idx, const StepArgs& a, int block, 
   }
   if (mode == MODE_EVEN2) {
     hipLaunchKernelGGL((k_even_pair<Q, COLL, ST>), grid, blk, lds, st, a);
-    return hipGetLastError();
-  }
-  if (mode == MODE_ODD2) {
-    hipLaunchKernelGGL((k_odd_pair<Q, COLL, ST>), grid, blk, lds, st, a);
     return hipGetLastError();
   }
   if (mode == MODE_ODD && idx == IDX_RUN)

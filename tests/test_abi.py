@@ -192,14 +192,8 @@ def test_launch_table_roundtrip():
     assert lbm.lbm_get_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F16DEV) == (128, 0)
     lbm.lbm_set_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F16DEV, *old)
     assert lbm.lbm_get_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F16DEV, full=True) == old
-    # two cells per thread exist for the odd and even kernels, not for the
-    # dense or the pipelined odd kernel; more than two nowhere
-    old_odd = lbm.lbm_get_launch(lbm.KERNEL_ODD, 19, lbm.STORE_F32, full=True)
-    lbm.lbm_set_launch(lbm.KERNEL_ODD, 19, lbm.STORE_F32, 256, 1, 0, 2)
-    assert lbm.lbm_get_launch(lbm.KERNEL_ODD, 19, lbm.STORE_F32, full=True) == (256, 1, 0, 2, 0)
-    lbm.lbm_set_launch(lbm.KERNEL_ODD, 19, lbm.STORE_F32, *old_odd)
-    expect(lbm.LBM_EINVAL, lbm.lbm_set_launch, lbm.KERNEL_DENSE, 19, lbm.STORE_F32, 256, 0, 0, 2)
-    expect(lbm.LBM_EINVAL, lbm.lbm_set_launch, lbm.KERNEL_ODD, 19, lbm.STORE_F32, 256, 1, 1, 2)
+    # two cells per thread exist for the even kernel only
+    expect(lbm.LBM_EINVAL, lbm.lbm_set_launch, lbm.KERNEL_ODD, 19, lbm.STORE_F32, 256, 1, 0, 2)
     expect(lbm.LBM_EINVAL, lbm.lbm_set_launch, lbm.KERNEL_EVEN, 19, lbm.STORE_F32, 256, 0, 0, 3)
     # residency caps: 0 or 2..16, AA kernels only, not with the pipelined odd kernel
     for bad in (1, 17, -1):

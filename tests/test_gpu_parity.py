@@ -1270,96 +1270,6 @@ def test_even_kernel_two_cells_per_thread_is_bitwise_identical(q, kind, storage)
         assert torch.equal(a, b), (float(d.max()), bad.shape[0], bad[:5].tolist())
 
 
-@pytest.mark.parametrize("q,kind,storage", [(19, lbm.COLL_TRT, lbm.STORE_F32),
-                                            (19, lbm.COLL_TRT, lbm.STORE_F64),
-                                            (19, lbm.COLL_SRT, lbm.STORE_F16DEV),
-                                            (19, lbm.COLL_MRT, lbm.STORE_F32DEV),
-                                            (27, lbm.COLL_CUMULANT, lbm.STORE_BF16DEV),
-                                            (27, lbm.COLL_CM, lbm.STORE_F32)])
-def test_odd_kernel_two_cells_per_thread_is_bitwise_identical(q, kind, storage):
-    """The run-form odd kernel with two cells per thread (2-wide gathers and
-    scatters where both cells lie in one run, single accesses where a run
-    starts at the second cell or it is past the last fluid cell) performs
-    each cell's arithmetic unchanged: identical PDFs to one cell per thread
-    after odd and even step counts, alone and in a batch that mixes index
-    forms, with boundary links, odd and even fluid-cell counts and an
-    unpadded odd stride."""
-    lab = inputs.random_mask((23, 21, 19), 0.3, seed=14, n_classes=3, class_fraction=0.5)
-    if np.count_nonzero(lab == 0) % 2 == 0:       # odd fluid-cell count
-        lab[np.unravel_index(np.flatnonzero(lab == 1)[0], lab.shape)] = 0
-    coll, bs, _ = _params(q, kind, 0.7, (1e-5, 0, 0), CLASSES)
-    dev_exp = 14 if storage == lbm.STORE_F16DEV else 0
-    old = lbm.lbm_get_launch(lbm.KERNEL_ODD, q, storage, full=True)
-    _say("odd two-cell kernel", q, kind, storage)
-    out = []
-    try:
-        for cpt in (1, 2):
-            cfg = list(old)
-            cfg[3] = cpt
-            lbm.lbm_set_launch(lbm.KERNEL_ODD, q, storage, *cfg)
-            doms = [lbm.SparseDomain(lab, 3, q, lbm.ORDER_BLOCKED),
-                    lbm.SparseDomain(lab[:, :, 1:], 3, q, lbm.ORDER_BLOCKED),
-                    lbm.SparseDomain(lab, 3, q, lbm.ORDER_BLOCKED, align=1),
-                    lbm.SparseDomain(lab[:, 2:, :], 7, q, lbm.ORDER_MORTON)]
-            assert doms[2].stride == doms[2].n_fluid and doms[2].stride % 2 == 1
-            sols = []
-            for j, d in enumerate(doms):
-                if j < 3:
-                    d.compact_runs(drop_index=j == 1)
-                s = lbm.Solver(d, storage, dev_exp)
-                _upload(s, _random_state(q, d.n_fluid, seed=j + 21), dev_exp)
-                sols.append(s)
-            for s in sols[:3]:
-                s.step(7, coll, bs)
-            batch = []
-            for j, d in enumerate(doms):
-                s = lbm.Solver(d, storage, dev_exp)
-                _upload(s, _random_state(q, d.n_fluid, seed=j + 40), dev_exp)
-                batch.append(s)
-            lbm.lbm_step_batch([s.state for s in batch], [coll] * 4, [bs] * 4, 6)
-            torch.cuda.synchronize()
-            out.append([s.pdf[:q * s.domain.stride].view(q, -1)[:, :s.domain.n_fluid].clone()
-                        for s in sols[:3] + batch])
-    finally:
-        lbm.lbm_set_launch(lbm.KERNEL_ODD, q, storage, *old)
-    for a, b in zip(*out):
-        d = (a.double() - b.double()).abs()
-        bad = torch.nonzero(d)
-        assert torch.equal(a, b), (float(d.max()), bad.shape[0], bad[:5].tolist())
-
-
-def test_odd_kernel_two_cells_per_thread_matches_oracle():
-    """FP64, run form only, two cells per thread in the odd step: 20 steps
-    against the sparse oracle within 1e-12 relative."""
-    q = 19
-    lab = inputs.random_mask((26, 19, 22), 0.35, seed=31, n_classes=3, class_fraction=0.5)
-    coll, bs, op = _params(q, lbm.COLL_TRT, 0.8, (1e-5, 0, 0), CLASSES)
-    old = lbm.lbm_get_launch(lbm.KERNEL_ODD, q, lbm.STORE_F64, full=True)
-    _say("odd two-cell kernel against the oracle")
-    try:
-        cfg = list(old)
-        cfg[3] = 2
-        lbm.lbm_set_launch(lbm.KERNEL_ODD, q, lbm.STORE_F64, *cfg)
-        dom = lbm.SparseDomain(lab, 3, q, lbm.ORDER_BLOCKED)
-        dom.compact_runs(drop_index=True)
-        sol = lbm.Solver(dom, lbm.STORE_F64)
-        f0 = _random_state(q, dom.n_fluid, seed=3)
-        _upload(sol, f0, 0)
-        sol.step(20, coll, bs)
-        torch.cuda.synchronize()
-    finally:
-        lbm.lbm_set_launch(lbm.KERNEL_ODD, q, lbm.STORE_F64, *old)
-    lay = oracle.sparse_build(lab, 3, q, order=2, align=64)
-    assert np.array_equal(lay.cells, dom.cells[:dom.n_fluid].cpu().numpy())
-    pdf = np.zeros(q * lay.stride)
-    for i in range(q):
-        pdf[i * lay.stride:i * lay.stride + lay.n_fluid] = f0[i]
-    ref = oracle.sparse_run(op, lay, pdf, 0, 20)
-    got = sol.pdf.cpu().numpy().reshape(q, -1)[:, :dom.n_fluid]
-    want = ref.reshape(q, -1)[:, :dom.n_fluid]
-    assert np.max(np.abs(got - want) / np.abs(want)) < 1e-12
-
-
 def test_convert_storage_formats():
     """lbm_convert: FP16 deviations convert to FP32 deviations and FP64
     exactly (value for value, at an odd step count, so in swapped slots),
