@@ -536,6 +536,12 @@ def main():
                     help="workgroup size of the odd-step kernel (default: the library's table)")
     ap.add_argument("--even-block", type=int, default=None, choices=[64, 128, 256],
                     help="the same for the even-step kernel")
+    ap.add_argument("--odd-xcd", type=int, default=None,
+                    help="tile order of the odd-step kernel over the XCDs: 0 dispatch order, "
+                         "1 one eighth per XCD, m >= 2 chunks of m tiles (default: the "
+                         "library's table)")
+    ap.add_argument("--even-xcd", type=int, default=None,
+                    help="the same for the even-step kernel")
     ap.add_argument("--odd-groups", type=int, default=None,
                     help="resident workgroups per CU of the odd-step kernel (0: uncapped; "
                          "default: the library's table)")
@@ -776,13 +782,15 @@ def packing_record(lbm, torch, costmodel, lab_dev, per, q, order, args, name, co
         cfg = list(lbm.lbm_get_launch(lbm.KERNEL_EVEN, q, storage, full=True))
         cfg[3] = args.even_cells
         lbm.lbm_set_launch(lbm.KERNEL_EVEN, q, storage, *cfg)
-    for kern, blk, g in ((lbm.KERNEL_ODD, args.odd_block, args.odd_groups),
-                         (lbm.KERNEL_EVEN, args.even_block, args.even_groups)):
+    for kern, blk, g, x in ((lbm.KERNEL_ODD, args.odd_block, args.odd_groups, args.odd_xcd),
+                            (lbm.KERNEL_EVEN, args.even_block, args.even_groups, args.even_xcd)):
         cfg = list(lbm.lbm_get_launch(kern, q, storage, full=True))
         if blk is not None:
             cfg[0] = blk
         if g is not None:
             cfg[4] = g
+        if x is not None:
+            cfg[1] = x
         lbm.lbm_set_launch(kern, q, storage, *cfg)
     sol = lbm.Solver(dom, storage, dev_exp)
     solve_bytes = dom.device_bytes() + sol.device_bytes()

@@ -415,7 +415,11 @@ lbm_status lbm_dense_step(lbm_dense_state* state, int32_t n_steps, const lbm_col
 enum { LBM_KERNEL_ODD = 0, LBM_KERNEL_EVEN = 1, LBM_KERNEL_DENSE = 2 };
 typedef struct {
   int32_t block;      /* threads per workgroup: 64, 128 or 256                 */
-  int32_t xcd_remap;  /* 1: contiguous tile ranges per XCD (8 XCDs)            */
+  int32_t xcd_remap;  /* tile order over the 8 XCDs (workgroup v runs on XCD  */
+                      /* v % 8): 0 = dispatch order; 1 = each XCD takes one    */
+                      /* contiguous eighth of the tiles; m in [2, 65536] =     */
+                      /* chunks of m consecutive tiles dealt round-robin to    */
+                      /* the XCDs                                              */
   int32_t pipelined;  /* odd kernel, block 256, compact index-list only: 1 =   */
                       /* persistent workgroups that load the next tile's       */
                       /* offsets during the current tile (same results)        */
@@ -435,8 +439,9 @@ typedef struct {
  * now on, process-wide (e.g. from an autotuner cache).  Changing it does
  * not change results except through workgroup-to-tile assignment, which
  * the arithmetic does not depend on.  Defaults (measured on MI355X): block
- * 256; XCD-aware tile order for the odd kernel only; two cells per thread
- * for even steps in 16-bit storage; D3Q19 FP32 and FP32-dev at most 4
+ * 256; XCD-aware tile order (chunks of 16 tiles) for the odd kernel only;
+ * two cells per thread for even steps in 16-bit storage; D3Q19 FP32 and
+ * FP32-dev at most 4
  * (odd) and 3 (even) workgroups per CU; D3Q19 FP64 even steps with block
  * 64, two cells per thread, at most 2 per CU; D3Q27 FP32 and FP32-dev
  * odd steps at most 3 per CU; everything else uncapped. */

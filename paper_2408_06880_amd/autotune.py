@@ -16,7 +16,7 @@ import math
 import os
 
 BLOCKS = (64, 128, 256)
-XCD = (0, 1)
+XCD = (0, 1, 16)        # dispatch order, one eighth per XCD, chunks of 16 tiles
 CELLS = (1, 2)          # cells per thread, even-step kernel only
 GROUPS = (0, 2, 3, 4)   # resident workgroups per CU (0: as registers allow)
 KERNEL_NAMES = {0: "odd", 1: "even", 2: "dense"}
@@ -33,8 +33,9 @@ def cache_key(device: str, kernel: int, q: int, storage: int, bucket: int) -> st
 
 def choose(timings: dict) -> tuple:
     """timings: {(block, xcd[, cells[, groups]]): seconds} -> the fastest
-    configuration; ties keep the larger block (fewer workgroups), then XCD
-    order on, then fewer cells per thread, then no residency cap."""
+    configuration; ties keep the larger block (fewer workgroups), then the
+    larger XCD order value, then fewer cells per thread, then no residency
+    cap."""
     best = None
     for cfg, t in timings.items():
         key = (t, -cfg[0], -cfg[1], *cfg[2:3], *(g if g else -1 for g in cfg[3:]))

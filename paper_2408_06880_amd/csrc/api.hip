@@ -64,7 +64,10 @@ void launch_defaults() {
       for (int st = 0; st < 5; ++st) {
         lbm_launch& c = g_launch[k][qi][st];
         c.block = 256;
-        c.xcd_remap = (k == LBM_KERNEL_ODD) ? 1 : 0;
+        // odd step: chunks of 16 tiles dealt round-robin to the XCDs
+        // (FP64 638 -> 618 us, FP32 357 -> 342 us against one contiguous
+        // eighth per XCD; chunks of 12-32 tiles measure the same)
+        c.xcd_remap = (k == LBM_KERNEL_ODD) ? 16 : 0;
         c.pipelined = 0;
         c.cells_per_thread = (k == LBM_KERNEL_EVEN && is16(st)) ? 2 : 1;
         c.max_groups_per_cu = 0;
@@ -317,6 +320,8 @@ lbm_status lbm_set_launch(int32_t kernel, int32_t q, int32_t storage, const lbm_
     return fail(LBM_EINVAL, "lbm_set_launch: bad kernel/q/storage");
   if (cfg->block != 64 && cfg->block != 128 && cfg->block != 256)
     return fail(LBM_EINVAL, "block must be 64, 128 or 256 (got %d)", cfg->block);
+  if (cfg->xcd_remap < 0 || cfg->xcd_remap > 65536)
+    return fail(LBM_EINVAL, "xcd_remap must be in [0, 65536] (got %d)", cfg->xcd_remap);
   if (cfg->pipelined != 0 && (cfg->pipelined != 1 || kernel != LBM_KERNEL_ODD || cfg->block != 256))
     return fail(LBM_EINVAL, "pipelined applies to the odd kernel with block 256 only");
   if (cfg->cells_per_thread < 0 || cfg->cells_per_thread > 2 ||

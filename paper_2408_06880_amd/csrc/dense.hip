@@ -49,7 +49,7 @@ __global__ __launch_bounds__(256) void k_dense_step(const DenseArgs a) {
   using T = typename SP::T;
   using R = typename SP::R;
   using L = Lattice<Q>;
-  const uint32_t tile = a.xcd_remap ? xcd_tile(blockIdx.x, a.ntiles) : blockIdx.x;
+  const uint32_t tile = xcd_tile(blockIdx.x, a.ntiles, a.xcd_remap);
   const uint32_t lin = tile * blockDim.x + threadIdx.x;
   if (lin >= a.N) return;
   T* __restrict__ pdf = static_cast<T*>(a.pdf);

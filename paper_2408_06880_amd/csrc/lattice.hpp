@@ -191,13 +191,26 @@ __device__ __forceinline__ uint32_t pos16(const Seg& g, int q, int i, int oi, ui
 }
 
 // XCD-aware tile order.  Workgroups are dispatched round-robin over the 8
-// XCDs (workgroup v runs on XCD v % 8); mapping the workgroups of one XCD to
-// one contiguous range of tiles keeps neighbouring tiles (and therefore the
-// neighbour gathers of the odd step) inside one XCD's L2.
-__device__ __forceinline__ uint32_t xcd_tile(uint32_t v, uint32_t n) {
+// XCDs (workgroup v runs on XCD v % 8).  mode 0: tile v (dispatch order).
+// mode 1: the workgroups of one XCD take one contiguous eighth of the
+// tiles.  mode m >= 2: chunks of m consecutive tiles are dealt round-robin
+// to the XCDs (chunk c of XCD x is tiles (8c + x) m .. (8c + x) m + m - 1);
+// tiles past the last full round of 8 m map to themselves.  Chunks keep the
+// neighbour gathers of the odd step (upstream rows a few hundred to a few
+// thousand list positions away) inside one XCD's L2 while all XCDs sweep
+// the arrays together; one eighth per XCD makes 8 separate sweeps of every
+// direction block.  Every mode is a bijection of [0, n).
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t v, uint32_t n, int32_t mode) {
+  if (mode <= 0) return v;
   const uint32_t x = v & 7u, local = v >> 3;
-  const uint32_t per = n >> 3, rem = n & 7u;
-  return x * per + (x < rem ? x : rem) + local;
+  if (mode == 1) {
+    const uint32_t per = n >> 3, rem = n & 7u;
+    return x * per + (x < rem ? x : rem) + local;
+  }
+  const uint32_t m = (uint32_t)mode, round = 8u * m, full = n / round;
+  if (v >= full * round) return v;
+  const uint32_t c = local / m, r = local - c * m;
+  return (c * 8u + x) * m + r;
 }
 
 // Segment of a tile: the last segment whose first tile is not after it

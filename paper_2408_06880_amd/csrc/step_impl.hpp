@@ -197,7 +197,7 @@ __device__ __forceinline__ void aa_cell(const Seg& g, uint32_t tile) {
 template <int Q, int COLL, int ST, int MODE, int IDX>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU))) void k_aa_step(const StepArgs a) {
-  const uint32_t tile = a.xcd_remap ? xcd_tile(blockIdx.x, a.ntiles) : blockIdx.x;
+  const uint32_t tile = xcd_tile(blockIdx.x, a.ntiles, a.xcd_remap);
   with_seg(a, tile, [&](const Seg& g) { aa_cell<Q, COLL, ST, MODE, IDX>(g, tile); });
 }
 
@@ -244,7 +244,7 @@ __device__ __forceinline__ void even_pair_cells(const Seg& g, uint32_t tile) {
 
 template <int Q, int COLL, int ST>
 __global__ __launch_bounds__(256) void k_even_pair(const StepArgs a) {
-  const uint32_t tile = a.xcd_remap ? xcd_tile(blockIdx.x, a.ntiles) : blockIdx.x;
+  const uint32_t tile = xcd_tile(blockIdx.x, a.ntiles, a.xcd_remap);
   with_seg(a, tile, [&](const Seg& g) { even_pair_cells<Q, COLL, ST>(g, tile); });
 }
 
@@ -271,7 +271,7 @@ __global__ __launch_bounds__(256) void k_odd_pipe(const StepArgs a) {
   const uint32_t G = gridDim.x;
   uint32_t v = blockIdx.x;
   if (v >= a.ntiles) return;
-  uint32_t tile = a.xcd_remap ? xcd_tile(v, a.ntiles) : v;
+  uint32_t tile = xcd_tile(v, a.ntiles, a.xcd_remap);
   uint32_t o[Q];
   with_seg(a, tile, [&](const Seg& g) { pipe_load_offsets<Q>(g, tile, o); });
   while (true) {
@@ -280,7 +280,7 @@ __global__ __launch_bounds__(256) void k_odd_pipe(const StepArgs a) {
     uint32_t tn = 0;
     uint32_t on[Q];
     if (has_next) {
-      tn = a.xcd_remap ? xcd_tile(vn, a.ntiles) : vn;
+      tn = xcd_tile(vn, a.ntiles, a.xcd_remap);
       with_seg(a, tn, [&](const Seg& gn) { pipe_load_offsets<Q>(gn, tn, on); });
     }
     with_seg(a, tile, [&](const Seg& g) {

@@ -358,7 +358,7 @@ def lbm_dense_step(state, n_steps, coll, stream=None):
           _stream(stream))
 
 
-def lbm_set_launch(kernel, q, storage, block=256, xcd_remap=1, pipelined=0, cells_per_thread=1,
+def lbm_set_launch(kernel, q, storage, block=256, xcd_remap=16, pipelined=0, cells_per_thread=1,
                    max_groups_per_cu=0):
     cfg = lbm_launch(block, xcd_remap, pipelined, cells_per_thread, max_groups_per_cu)
     _call("lbm_set_launch", kernel, q, storage, ctypes.byref(cfg))

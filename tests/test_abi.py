@@ -181,12 +181,12 @@ def test_launch_table_roundtrip():
     assert lbm.lbm_get_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F32, full=True) == (256, 0, 0, 1, 0)
     # measured residency caps: D3Q19 FP32 and FP32-dev odd 4 and even 3; FP64
     # even step 64-thread workgroups, two cells per thread, 2 per CU
-    assert lbm.lbm_get_launch(lbm.KERNEL_ODD, 19, lbm.STORE_F32, full=True) == (256, 1, 0, 1, 4)
+    assert lbm.lbm_get_launch(lbm.KERNEL_ODD, 19, lbm.STORE_F32, full=True) == (256, 16, 0, 1, 4)
     assert lbm.lbm_get_launch(lbm.KERNEL_EVEN, 19, lbm.STORE_F32, full=True) == (256, 0, 0, 1, 3)
     assert lbm.lbm_get_launch(lbm.KERNEL_EVEN, 19, lbm.STORE_F64, full=True) == (64, 0, 0, 2, 2)
-    assert lbm.lbm_get_launch(lbm.KERNEL_ODD, 19, lbm.STORE_F64, full=True) == (256, 1, 0, 1, 0)
+    assert lbm.lbm_get_launch(lbm.KERNEL_ODD, 19, lbm.STORE_F64, full=True) == (256, 16, 0, 1, 0)
     assert lbm.lbm_get_launch(lbm.KERNEL_EVEN, 19, lbm.STORE_F32DEV, full=True) == (256, 0, 0, 1, 3)
-    assert lbm.lbm_get_launch(lbm.KERNEL_ODD, 27, lbm.STORE_F32, full=True) == (256, 1, 0, 1, 3)
+    assert lbm.lbm_get_launch(lbm.KERNEL_ODD, 27, lbm.STORE_F32, full=True) == (256, 16, 0, 1, 3)
     assert lbm.lbm_get_launch(lbm.KERNEL_DENSE, 19, lbm.STORE_F32, full=True)[4] == 0
     lbm.lbm_set_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F16DEV, 128, 0)
     assert lbm.lbm_get_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F16DEV) == (128, 0)
@@ -195,6 +195,9 @@ def test_launch_table_roundtrip():
     # two cells per thread exist for the even kernel only
     expect(lbm.LBM_EINVAL, lbm.lbm_set_launch, lbm.KERNEL_ODD, 19, lbm.STORE_F32, 256, 1, 0, 2)
     expect(lbm.LBM_EINVAL, lbm.lbm_set_launch, lbm.KERNEL_EVEN, 19, lbm.STORE_F32, 256, 0, 0, 3)
+    # tile order: 0, 1 or a chunk of 2..65536 tiles
+    for bad in (-1, 65537):
+        expect(lbm.LBM_EINVAL, lbm.lbm_set_launch, lbm.KERNEL_ODD, 19, lbm.STORE_F32, 256, bad)
     # residency caps: 0 or 2..16, AA kernels only, not with the pipelined odd kernel
     for bad in (1, 17, -1):
         expect(lbm.LBM_EINVAL, lbm.lbm_set_launch, lbm.KERNEL_ODD, 19, lbm.STORE_F32, 256, 1, 0,

@@ -1190,19 +1190,23 @@ def test_default_launch_odd_and_even_strides_agree(storage):
                                             (19, lbm.COLL_TRT, lbm.STORE_F64),
                                             (27, lbm.COLL_CM, lbm.STORE_F16DEV)])
 def test_residency_caps_are_bitwise_identical(q, kind, storage):
-    """Capping the resident workgroups per CU (reserved LDS) changes where
-    and when tiles run, not the arithmetic: PDFs after odd and even step
-    counts are identical for every cap and block size, alone and batched."""
+    """Capping the resident workgroups per CU (reserved LDS) and the tile
+    order over the XCDs change where and when tiles run, not the
+    arithmetic: PDFs after odd and even step counts are identical for every
+    cap, block size and tile order (dispatch order, one eighth per XCD,
+    chunks of 3 and 16 tiles, whose last partial round maps to itself),
+    alone and batched."""
     lab = inputs.random_mask((26, 22, 20), 0.3, seed=21, n_classes=3, class_fraction=0.5)
     coll, bs, _ = _params(q, kind, 0.7, (1e-5, 0, 0), CLASSES)
     dev_exp = 14 if storage == lbm.STORE_F16DEV else 0
     old = [lbm.lbm_get_launch(k, q, storage, full=True) for k in (0, 1)]
     out = []
     try:
-        for block, g in ((256, 0), (256, 2), (256, 4), (128, 3), (64, 16)):
+        for block, g, x in ((256, 0, None), (256, 2, 0), (256, 4, 1), (128, 3, 3),
+                            (64, 16, 16), (64, 0, 3)):
             for k in (0, 1):
                 b0, x0, _, c0, _ = old[k]
-                lbm.lbm_set_launch(k, q, storage, block, x0, 0, c0, g)
+                lbm.lbm_set_launch(k, q, storage, block, x0 if x is None else x, 0, c0, g)
             sols = []
             for j, sub in enumerate((lab, lab[:, 1:, :])):
                 d = lbm.SparseDomain(sub, 3, q, lbm.ORDER_BLOCKED)
