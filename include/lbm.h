@@ -155,6 +155,11 @@ typedef struct {
                          /* index16 and index                                    */
   const int32_t* links;  /* device, 2*n_links or NULL when n_links == 0        */
   int64_t t;             /* steps taken. t even: populations in natural slots  */
+  void* link_vel;        /* device link-velocity buffer of this state          */
+                         /* (lbm_link_vel_prepare), or NULL                    */
+  int64_t link_vel_t;    /* t at which link_vel holds the velocities (set by   */
+                         /* every step); -1: holds nothing (set it so whenever */
+                         /* the PDF-list is written other than by the library) */
 } lbm_state;
 
 /* Collision operator (Section "Lattice Boltzmann Method" and "Code
@@ -254,6 +259,30 @@ lbm_status lbm_compress_index(const lbm_layout* layout, const int32_t* index, vo
 uint64_t lbm_runs_header_bytes(const lbm_layout* layout);
 lbm_status lbm_compress_runs(const lbm_layout* layout, const int32_t* index, void* runs,
                              uint64_t capacity, uint64_t* needed, void* stream);
+
+/* Link-velocity buffer (optional; no counterpart in the paper).  The
+ * pressure rule of Section "Sparse Boundary Conditions" as this library
+ * states it needs the velocity of each cell that has an outlet link before
+ * every step; without the buffer the link update gathers all q populations
+ * of such a cell (one cache line each).  With it, every step kernel also
+ * writes the velocity of the cells that have links, the step calls set
+ * lbm_state.link_vel_t = t after each step, and a link update at time t
+ * reads the velocities there when link_vel_t == t (else it gathers).
+ * lbm_init_equilibrium and lbm_convert set link_vel_t = -1 on the state
+ * they write; a caller that writes a PDF-list by other means (an upload, a
+ * restored checkpoint) sets it to -1 too.  Results are bitwise the same
+ * with and without the buffer.
+ *  lbm_link_vel_bytes: device bytes for `layout` (0 when it has no links;
+ *      host only).
+ *  lbm_link_vel_prepare: links device int32[2*n_links] from
+ *      lbm_build_sparse (same layout); link_vel device buffer of
+ *      lbm_link_vel_bytes(layout) bytes: marks the cells with links, in
+ *      stream order (asynchronous).  Set lbm_state.link_vel to it.  One
+ *      buffer belongs to one state: states stepped in one batch, or
+ *      concurrently, need buffers of their own. */
+uint64_t lbm_link_vel_bytes(const lbm_layout* layout);
+lbm_status lbm_link_vel_prepare(const lbm_layout* layout, const int32_t* links, void* link_vel,
+                                void* stream);
 
 /* Change a state's storage format (the deviation storage of the FP16/BF16
  * formats; no counterpart in the paper): every slot of src's PDF-list,
@@ -356,7 +385,7 @@ lbm_status lbm_step_batch(lbm_state* const* states, const lbm_collision* const* 
  * allocation): the same steps, launches and results as lbm_step_batch with
  * the same arguments, but the segment tables go into a fixed device array
  * inside the library instead of a caller workspace.  The array holds the
- * tables of LBM_STEP_BATCH_NOALLOC_MAX states (about 320 KiB); each device
+ * tables of LBM_STEP_BATCH_NOALLOC_MAX states (about 370 KiB); each device
  * the library runs on keeps its own copy until the process ends, and the
  * call allocates nothing.
  *  n_states  1 .. LBM_STEP_BATCH_NOALLOC_MAX; more returns LBM_ENOMEM.
@@ -457,9 +486,10 @@ lbm_status lbm_copy(void* dst, const void* src, uint64_t bytes, void* stream);
 /* Message of the last failing call on the calling thread (owned by the
  * library, valid until that thread's next call; empty when none failed). */
 const char* lbm_last_error(void);
-/* Version of this interface: 6 (launch table with residency caps, unsigned
+/* Version of this interface: 7 (launch table with residency caps, unsigned
  * 32-bit positions, optional int32 index-list next to the run form, batch
- * segment tables in a caller workspace, batch steps without allocation). */
+ * segment tables in a caller workspace, batch steps without allocation,
+ * link-velocity buffer in the state). */
 int32_t lbm_abi_version(void);
 
 #ifdef __cplusplus

@@ -232,6 +232,33 @@ RunsView runs_view(const lbm_layout& L, const void* p) {
   return v;
 }
 
+// Sub-buffers of a link-velocity buffer of `layout` starting at `p`.
+struct LinkVelView {
+  uint64_t* mask;
+  uint32_t* woff;
+  void* vel;
+  uint32_t nw;
+  uint64_t bytes;
+};
+
+LinkVelView link_vel_view(const lbm_layout& L, void* p) {
+  LinkVelView v;
+  v.nw = (uint32_t)(((uint64_t)L.stride + kRunWave - 1) / kRunWave);
+  const uint64_t mask_b = align256(8 * (uint64_t)v.nw);
+  const uint64_t woff_b = align256(4 * ((uint64_t)v.nw + 1));
+  v.bytes = mask_b + woff_b + align256(3 * 8 * (uint64_t)L.n_links);
+  v.mask = nullptr;
+  v.woff = nullptr;
+  v.vel = nullptr;
+  if (p) {
+    char* c = (char*)p;
+    v.mask = (uint64_t*)c;
+    v.woff = (uint32_t*)(c + mask_b);
+    v.vel = c + mask_b + woff_b;
+  }
+  return v;
+}
+
 // Index form the odd step reads for a state: runs, else compact, else int32.
 int index_form(const lbm_state* s) {
   return s->runs ? IDX_RUN : (s->index16 ? IDX_16 : IDX_I32);
@@ -256,6 +283,12 @@ Seg make_seg(const lbm_state* s, const lbm_collision* c) {
     g.rmask = r.mask;
     g.rval = r.val;
   }
+  if (s->link_vel && s->layout.n_links > 0) {
+    LinkVelView v = link_vel_view(s->layout, s->link_vel);
+    g.lmask = v.mask;
+    g.lwoff = v.woff;
+    g.lvel = v.vel;
+  }
   if (c) {
     coll_rates(c, g.om1, g.om2, g.rates);
     for (int a = 0; a < 3; ++a) g.F[a] = c->force[a];
@@ -268,7 +301,8 @@ Seg make_seg(const lbm_state* s, const lbm_collision* c) {
 
 // Boundary links of one state before a step.  natural: the populations sit
 // in their natural slots (AA at even t, every pull step); the pressure rule
-// reads the cell's velocity from them (coll supplies the force).
+// reads the cell's velocity from them (coll supplies the force), or from the
+// state's link-velocity buffer when a step kernel filled it at this t.
 lbm_status link_update(const lbm_state* s, const lbm_collision* c, const lbm_bspec* bs,
                        bool natural, hipStream_t st) {
   if (s->layout.n_links == 0) return LBM_OK;
@@ -276,6 +310,7 @@ lbm_status link_update(const lbm_state* s, const lbm_collision* c, const lbm_bsp
   memset(&la, 0, sizeof(la));
   la.g = make_seg(s, c);
   la.natural = natural ? 1 : 0;
+  la.use_vel = (la.g.lmask && s->link_vel_t == s->t) ? 1 : 0;
   la.pdf = s->pdf;
   la.links = s->links;
   la.n_links = (uint32_t)s->layout.n_links;
@@ -299,10 +334,10 @@ lbm_status link_update(const lbm_state* s, const lbm_collision* c, const lbm_bsp
 }
 
 hipError_t launch_aa(int q, int coll, int storage, int mode, int idx, const StepArgs& a,
-                     const lbm_launch& cfg, hipStream_t st) {
+                     const lbm_launch& cfg, bool links, hipStream_t st) {
   const uint32_t lds = cap_lds_bytes(cfg.max_groups_per_cu);
-  if (q == 19) return launch_aa_q19(coll, storage, mode, idx, a, cfg.block, lds, st);
-  return launch_aa_q27(coll, storage, mode, idx, a, cfg.block, lds, st);
+  if (q == 19) return launch_aa_q19(coll, storage, mode, idx, a, cfg.block, lds, links, st);
+  return launch_aa_q27(coll, storage, mode, idx, a, cfg.block, lds, links, st);
 }
 
 uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
@@ -311,7 +346,7 @@ uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); 
 
 extern "C" {
 
-int32_t lbm_abi_version(void) { return 6; }
+int32_t lbm_abi_version(void) { return 7; }
 
 const char* lbm_last_error(void) { return g_err.c_str(); }
 
@@ -461,6 +496,30 @@ lbm_status lbm_compress_index(const lbm_layout* L, const int32_t* index, void* i
   return LBM_OK;
 }
 
+// ------------------------------------------------ link-velocity buffer
+uint64_t lbm_link_vel_bytes(const lbm_layout* L) {
+  if (!L || (L->q != 19 && L->q != 27) || L->stride < 0 || L->n_links <= 0) return 0;
+  return link_vel_view(*L, nullptr).bytes;
+}
+
+lbm_status lbm_link_vel_prepare(const lbm_layout* L, const int32_t* links, void* link_vel,
+                                void* stream) {
+  if (!L) return fail(LBM_EINVAL, "layout is NULL");
+  lbm_status rc = check_layout(*L);
+  if (rc) return rc;
+  if (L->n_links == 0) return LBM_OK;
+  if (!links || !link_vel) return fail(LBM_EINVAL, "links/link_vel is NULL");
+  if (L->n_links > 0xffffffffll) return fail(LBM_ERANGE, "too many links");
+  LinkVelView v = link_vel_view(*L, link_vel);
+  if (v.nw == 0) return LBM_OK;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(launch_link_mask(links, (uint32_t)L->n_links, (uint32_t)L->stride, v.nw, v.mask, v.woff,
+                           st),
+          "link cells");
+  HIP_TRY(launch_exclusive_scan(v.nw, v.woff, st), "link entries");
+  return LBM_OK;
+}
+
 // ------------------------------------------- run-compressed index-list
 uint64_t lbm_runs_header_bytes(const lbm_layout* L) {
   if (!L || (L->q != 19 && L->q != 27) || L->stride < 0) return 0;
@@ -522,6 +581,7 @@ lbm_status lbm_convert(const lbm_state* src, lbm_state* dst, void* stream) {
                          (hipStream_t)stream),
           "convert");
   dst->t = src->t;
+  dst->link_vel_t = -1;
   return LBM_OK;
 }
 
@@ -537,6 +597,7 @@ lbm_status lbm_init_equilibrium(lbm_state* s, double rho0, const double* u0, voi
                         (hipStream_t)stream),
             "init");
   s->t = 0;
+  s->link_vel_t = -1;
   return LBM_OK;
 }
 
@@ -545,6 +606,7 @@ lbm_status lbm_init_equilibrium(lbm_state* s, double rho0, const double* u0, voi
 struct LaunchGroup {
   int mode, form;
   uint32_t first, nseg, ntiles;
+  bool links;  // some segment has a link-velocity buffer
 };
 
 static uint64_t seg_table_bytes(int64_t n) { return align256((uint64_t)n * sizeof(Seg)); }
@@ -577,24 +639,26 @@ static lbm_status step_group(lbm_state* const* states, const lbm_collision* cons
   // its own; even steps never read indices.
   for (int form = IDX_I32; form <= IDX_RUN; ++form) {
     LaunchGroup gr{form == IDX_16 && cfg_odd.pipelined == 1 ? MODE_ODD_PIPE : MODE_ODD, form,
-                   (uint32_t)segs.size(), 0, 0};
+                   (uint32_t)segs.size(), 0, 0, false};
     for (int32_t j = 0; j < n; ++j) {
       if (states[j]->layout.n_fluid == 0 || index_form(states[j]) != form) continue;
       Seg g = make_seg(states[j], colls[j]);
       g.tile0 = gr.ntiles;
       gr.ntiles += ceil_div(g.nf, (uint64_t)cfg_odd.block);
+      gr.links = gr.links || g.lmask != nullptr;
       segs.push_back(g);
       gr.nseg += 1;
     }
     if (gr.nseg > 0) odd_groups.push_back(gr);
   }
   {
-    LaunchGroup gr{cpt == 2 ? MODE_EVEN2 : MODE_EVEN, IDX_I32, (uint32_t)segs.size(), 0, 0};
+    LaunchGroup gr{cpt == 2 ? MODE_EVEN2 : MODE_EVEN, IDX_I32, (uint32_t)segs.size(), 0, 0, false};
     for (int32_t j = 0; j < n; ++j) {
       if (states[j]->layout.n_fluid == 0) continue;
       Seg g = make_seg(states[j], colls[j]);
       g.tile0 = gr.ntiles;
       gr.ntiles += ceil_div(g.nf, (uint64_t)cfg_even.block * cpt);
+      gr.links = gr.links || g.lmask != nullptr;
       segs.push_back(g);
       gr.nseg += 1;
     }
@@ -626,9 +690,13 @@ static lbm_status step_group(lbm_state* const* states, const lbm_collision* cons
         a.seg0 = segs[gr.first];
       else
         a.segs = table + gr.first;
-      HIP_TRY(launch_aa(q, kind, storage, gr.mode, gr.form, a, cfg, st), "AA step");
+      HIP_TRY(launch_aa(q, kind, storage, gr.mode, gr.form, a, cfg, gr.links, st), "AA step");
     }
-    for (int32_t j = 0; j < n; ++j) states[j]->t += 1;
+    // the step kernels wrote the velocities of the cells with links
+    for (int32_t j = 0; j < n; ++j) {
+      states[j]->t += 1;
+      states[j]->link_vel_t = states[j]->link_vel ? states[j]->t : -1;
+    }
   }
   return LBM_OK;
 }
@@ -678,13 +746,14 @@ lbm_status lbm_step_pull(lbm_state* s, void** spare, int32_t n_steps, const lbm_
       a.seg0 = g;
       a.nseg = 1;
       a.ntiles = ceil_div(g.nf, (uint64_t)cfg.block);
-      HIP_TRY(launch_aa(s->layout.q, c->kind, s->storage, MODE_PULL, idx, a, cfg, st),
+      HIP_TRY(launch_aa(s->layout.q, c->kind, s->storage, MODE_PULL, idx, a, cfg, true, st),
               "pull step");
       void* tmp = s->pdf;
       s->pdf = *spare;
       *spare = tmp;
     }
     s->t += 1;
+    s->link_vel_t = s->link_vel ? s->t : -1;
   }
   return LBM_OK;
 }

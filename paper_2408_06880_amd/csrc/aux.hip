@@ -140,6 +140,37 @@ __device__ __forceinline__ uint32_t link_cell(const LinkArgs& a, uint32_t l) {
   return (uint32_t)a.links[2 * l] - (uint32_t)opp(i) * a.g.S;
 }
 
+// Updated value of one link slot v (direction and class in meta; class type
+// 1 or 2) at the cell's velocity u.
+template <int Q, int ST>
+__device__ __forceinline__ typename Store<ST>::T link_slot(const LinkArgs& a, int meta,
+                                                           typename Store<ST>::T v,
+                                                           typename Store<ST>::R ux,
+                                                           typename Store<ST>::R uy,
+                                                           typename Store<ST>::R uz) {
+  using SP = Store<ST>;
+  using R = typename SP::R;
+  const int i = meta & 0xff, cls = (meta >> 8) & 0xff;
+  int cx, cy, cz;
+  double w;
+  dir_of<Q>(i, cx, cy, cz, w);
+  R dv = SP::load(v, R(w), R(a.inv_scale));
+  if (a.type[cls] == 1) {
+    dv = dv + R(6.0 * w * (cx * a.u[cls][0] + cy * a.u[cls][1] + cz * a.u[cls][2]));
+  } else {
+    const R cu = R(cx) * ux + R(cy) * uy + R(cz) * uz;
+    const R uu = ux * ux + uy * uy + uz * uz;
+    dv = -dv + R(2.0 * w * (a.rho[cls] - 1.0)) +
+         R(2.0 * w * a.rho[cls]) * (R(4.5) * cu * cu - R(1.5) * uu);
+  }
+  return SP::store(dv, R(w), R(a.scale));
+}
+
+__device__ __forceinline__ int link_type(const LinkArgs& a, int meta) {
+  const int cls = (meta >> 8) & 0xff;
+  return cls < a.n_classes ? a.type[cls] : 0;
+}
+
 template <int Q, int ST, bool ODD_T>
 __global__ __launch_bounds__(256) void k_links(const LinkArgs a) {
   using SP = Store<ST>;
@@ -167,8 +198,7 @@ __global__ __launch_bounds__(256) void k_links(const LinkArgs a) {
     if (on[m]) {
       pos[m] = (uint32_t)a.links[2 * l];
       meta[m] = a.links[2 * l + 1];
-      const int cls = (meta[m] >> 8) & 0xff;
-      pressure = pressure || (cls < a.n_classes && a.type[cls] == 2);
+      pressure = pressure || link_type(a, meta[m]) == 2;
     }
   }
 #pragma unroll
@@ -178,39 +208,46 @@ __global__ __launch_bounds__(256) void k_links(const LinkArgs a) {
   if (pressure) {
     R d[Q];
     gather_post<Q, ST, ODD_T>(a.g, k, d);
-    R drho = 0, jx = 0, jy = 0, jz = 0;
-#pragma unroll
-    for (int j = 0; j < Q; ++j) {
-      drho += d[j];
-      jx += R(Lattice<Q>::cx[j]) * d[j];
-      jy += R(Lattice<Q>::cy[j]) * d[j];
-      jz += R(Lattice<Q>::cz[j]) * d[j];
-    }
-    const R r = R(1) + drho;
-    ux = (jx - R(0.5) * R(a.g.F[0])) / r;
-    uy = (jy - R(0.5) * R(a.g.F[1])) / r;
-    uz = (jz - R(0.5) * R(a.g.F[2])) / r;
+    cell_velocity<Q, R>(d, a.g.F, ux, uy, uz);
   }
 #pragma unroll
-  for (int m = 0; m < Q - 1; ++m) {
-    if (!on[m]) continue;
-    const int i = meta[m] & 0xff, cls = (meta[m] >> 8) & 0xff;
-    const int type = cls < a.n_classes ? a.type[cls] : 0;
-    if (type == 0) continue;
-    int cx, cy, cz;
-    double w;
-    dir_of<Q>(i, cx, cy, cz, w);
-    R dv = SP::load(v[m], R(w), R(a.inv_scale));
-    if (type == 1) {
-      dv = dv + R(6.0 * w * (cx * a.u[cls][0] + cy * a.u[cls][1] + cz * a.u[cls][2]));
-    } else {
-      const R cu = R(cx) * ux + R(cy) * uy + R(cz) * uz;
-      const R uu = ux * ux + uy * uy + uz * uz;
-      dv = -dv + R(2.0 * w * (a.rho[cls] - 1.0)) +
-           R(2.0 * w * a.rho[cls]) * (R(4.5) * cu * cu - R(1.5) * uu);
-    }
-    pdf[pos[m]] = SP::store(dv, R(w), R(a.scale));
+  for (int m = 0; m < Q - 1; ++m)
+    if (on[m] && link_type(a, meta[m]) != 0)
+      pdf[pos[m]] = link_slot<Q, ST>(a, meta[m], v[m], ux, uy, uz);
+}
+
+// The same update when the step kernel before it left the velocity of every
+// cell with links in the link-velocity buffer: no thread reads a slot that
+// another one writes, so one thread takes one link.
+template <int Q, int ST>
+__global__ __launch_bounds__(256) void k_links_vel(const LinkArgs a) {
+  using SP = Store<ST>;
+  using T = typename SP::T;
+  using R = typename SP::R;
+  const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= a.n_links) return;
+  const uint32_t pos = (uint32_t)a.links[2 * l];
+  const int meta = a.links[2 * l + 1];
+  const int type = link_type(a, meta);
+  if (type == 0) return;
+  LBM_GLOBAL T* pdf = gp(static_cast<T*>(a.pdf));
+  const T v = pdf[pos];
+  R ux = 0, uy = 0, uz = 0;
+  if (type == 2) {
+    const uint32_t k = pos - (uint32_t)opp(meta & 0xff) * a.g.S;
+    const uint32_t w = k / kRunWave;
+    const LBM_GLOBAL R* u = gp(static_cast<const R*>(a.g.lvel)) +
+                            3 * (size_t)link_entry(gp(a.g.lmask)[w], gp(a.g.lwoff)[w], k);
+    ux = u[0];
+    uy = u[1];
+    uz = u[2];
   }
+  pdf[pos] = link_slot<Q, ST>(a, meta, v, ux, uy, uz);
+}
+
+template <int Q, int ST>
+static void launch_links_vel_st(const LinkArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL((k_links_vel<Q, ST>), dim3((a.n_links + 255) / 256), dim3(256), 0, st, a);
 }
 
 template <int Q, bool ODD_T>
@@ -229,6 +266,17 @@ static hipError_t launch_links_qt(int storage, const LinkArgs& a, hipStream_t st
 
 template <int Q>
 static hipError_t launch_links_q(int storage, const LinkArgs& a, hipStream_t st) {
+  if (a.use_vel) {
+    switch (storage) {
+      case ST_F64: launch_links_vel_st<Q, ST_F64>(a, st); break;
+      case ST_F32: launch_links_vel_st<Q, ST_F32>(a, st); break;
+      case ST_F16DEV: launch_links_vel_st<Q, ST_F16DEV>(a, st); break;
+      case ST_BF16DEV: launch_links_vel_st<Q, ST_BF16DEV>(a, st); break;
+      case ST_F32DEV: launch_links_vel_st<Q, ST_F32DEV>(a, st); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   return a.natural ? launch_links_qt<Q, false>(storage, a, st)
                    : launch_links_qt<Q, true>(storage, a, st);
 }
@@ -238,6 +286,38 @@ hipError_t launch_links(int storage, const LinkArgs& a, hipStream_t st) {
   if (a.q == 19) return launch_links_q<19>(storage, a, st);
   if (a.q == 27) return launch_links_q<27>(storage, a, st);
   return hipErrorInvalidValue;
+}
+
+// Link-velocity buffer set-up: one bit per cell that has a link.
+__global__ __launch_bounds__(256) void k_link_mask_clear(uint64_t* mask, uint32_t nw) {
+  const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w < nw) mask[w] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_link_mask_mark(const int32_t* links, uint32_t n_links,
+                                                        uint32_t S, uint32_t nw, uint64_t* mask) {
+  const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= n_links) return;
+  const int i = links[2 * l + 1] & 0xff;
+  const uint32_t k = (uint32_t)links[2 * l] - (uint32_t)opp(i) * S;
+  if (k / kRunWave < nw) atomicOr((unsigned long long*)&mask[k / kRunWave], 1ull << (k % kRunWave));
+}
+
+__global__ __launch_bounds__(256) void k_link_mask_count(const uint64_t* mask, uint32_t nw,
+                                                         uint32_t* woff) {
+  const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w < nw) woff[w] = (uint32_t)__popcll(mask[w]);
+}
+
+hipError_t launch_link_mask(const int32_t* links, uint32_t n_links, uint32_t S,
+                            uint32_t nw, uint64_t* mask, uint32_t* woff, hipStream_t st) {
+  const dim3 b(256);
+  hipLaunchKernelGGL(k_link_mask_clear, dim3((nw + 255) / 256), b, 0, st, mask, nw);
+  if (n_links > 0)
+    hipLaunchKernelGGL(k_link_mask_mark, dim3((n_links + 255) / 256), b, 0, st, links, n_links, S,
+                       nw, mask);
+  hipLaunchKernelGGL(k_link_mask_count, dim3((nw + 255) / 256), b, 0, st, mask, nw, woff);
+  return hipGetLastError();
 }
 
 template <int Q, int ST, bool ODD_T, class O>

@@ -10,17 +10,20 @@
 namespace lbm {
 
 // AA step kernels (step_q19.hip, step_q27.hip); mode 0 even, 1 odd, 2 pull
-// (lds: dynamic LDS bytes reserved per workgroup, to cap residency)
+// (lds: dynamic LDS bytes reserved per workgroup, to cap residency; links:
+// some solve of the launch has a link-velocity buffer)
 hipError_t launch_aa_q19(int coll, int storage, int mode, int idx, const StepArgs& a,
-                         int block, uint32_t lds, hipStream_t st);
+                         int block, uint32_t lds, bool links, hipStream_t st);
 hipError_t launch_aa_q27(int coll, int storage, int mode, int idx, const StepArgs& a,
-                         int block, uint32_t lds, hipStream_t st);
+                         int block, uint32_t lds, bool links, hipStream_t st);
 
 // Boundary-class coefficients of one solve, precomputed on the host:
 // for class c, type[c] in {0 noslip, 1 UBB, 2 pressure}; u[c][3]; rho[c].
 // g describes the solve (buffers, index forms, force, 16-bit scale) for the
 // gather of a cell's velocity; natural = 1 when the populations sit in
-// their natural slots (even t of the AA pattern, every pull step).
+// their natural slots (even t of the AA pattern, every pull step);
+// use_vel = 1 reads the velocity that the last step kernel wrote into the
+// link-velocity buffer (g.lmask, g.lwoff, g.lvel) instead of gathering it.
 struct LinkArgs {
   void* pdf;
   const int32_t* links;
@@ -28,6 +31,8 @@ struct LinkArgs {
   int32_t q;
   int32_t n_classes;
   int32_t natural;
+  int32_t use_vel;
+  int32_t pad;
   int32_t type[8];
   double u[8][3];
   double rho[8];
@@ -39,6 +44,11 @@ struct LinkArgs {
 hipError_t launch_init(int q, int storage, void* pdf, uint32_t S, uint32_t nf, double rho0,
                        const double u0[3], float scale, hipStream_t st);
 hipError_t launch_links(int storage, const LinkArgs& a, hipStream_t st);
+// Link-velocity buffer: mark the cells of the n links in mask (nw words,
+// cleared first) and write their popcounts to woff[0..nw) (the caller scans
+// them).
+hipError_t launch_link_mask(const int32_t* links, uint32_t n_links, uint32_t S,
+                            uint32_t nw, uint64_t* mask, uint32_t* woff, hipStream_t st);
 hipError_t launch_moments(int q, int storage, const Seg& g, bool odd_t, bool out_f64, void* rho,
                           void* u, hipStream_t st);
 // Reductions: first pass writes 5 doubles per tile of kRedBlock cells into

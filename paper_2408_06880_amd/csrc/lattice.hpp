@@ -104,6 +104,28 @@ struct Store<ST_BF16DEV> {
   }
 };
 
+// Velocity of a cell from its post-collision deviations d (natural order) at
+// the current time, for the pressure outlet's anti-bounce-back: the
+// half-force velocity u = (sum_i c_i d_i - F/2) / rho.  The link update and
+// the step kernels that hand it on both use this one expression, so the two
+// routes give the same bits.
+template <int Q, class R>
+__device__ __forceinline__ void cell_velocity(const R (&d)[Q], const double (&F)[3], R& ux,
+                                              R& uy, R& uz) {
+  R drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    drho += d[j];
+    jx += R(Lattice<Q>::cx[j]) * d[j];
+    jy += R(Lattice<Q>::cy[j]) * d[j];
+    jz += R(Lattice<Q>::cz[j]) * d[j];
+  }
+  const R r = R(1) + drho;
+  ux = (jx - R(0.5) * R(F[0])) / r;
+  uy = (jy - R(0.5) * R(F[1])) / r;
+  uz = (jz - R(0.5) * R(F[2])) / r;
+}
+
 // ---------------------------------------------------------------------------
 // Launch arguments.  One launch advances one or more independent solves
 // ("segments"); segment s owns workgroup tiles [tile0_s, tile0_{s+1}).  A
@@ -127,6 +149,17 @@ enum IndexForm { IDX_I32 = 0, IDX_16 = 1, IDX_RUN = 2 };
 // Run-compressed index-list: groups of kRunWave list positions (one wave).
 constexpr uint32_t kRunWave = 64;
 
+// Link-velocity buffer of a solve with boundary links (parts 256-byte
+// aligned): uint64 mask[W] (bit l of wave w: cell 64w + l has a link),
+// uint32 woff[W + 1] (exclusive prefix of the mask popcounts), then three
+// values of the compute type per marked cell, in list order (8 bytes per
+// value reserved).  Entry of cell k: woff[k/64] + popcount of the mask bits
+// below k % 64.
+__device__ __forceinline__ uint32_t link_entry(uint64_t m, uint32_t woff, uint32_t k) {
+  const uint32_t b = k & (kRunWave - 1);
+  return woff + (uint32_t)__builtin_popcountll(m & ((1ull << b) - 1ull));
+}
+
 struct Seg {
   void* pdf;               // PDF-list of this solve
   void* dst;               // pull scheme only: the second PDF-list written this step
@@ -136,6 +169,9 @@ struct Seg {
   const uint32_t* rvoff;   // run form: first value of each wave, or null
   const uint64_t* rmask;   // run form: run-start masks [wave][direction]
   const int32_t* rval;     // run form: run values
+  const uint64_t* lmask;   // link velocities: cells with links, bit per lane [wave]
+  const uint32_t* lwoff;   // link velocities: first entry of each wave
+  void* lvel;              // link velocities: 3 values of the compute type per entry
   uint32_t ntiles16;       // tiles of the compact index-list
   uint32_t S;              // stride
   uint32_t nf;             // fluid cells

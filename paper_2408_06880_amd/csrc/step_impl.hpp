@@ -113,9 +113,38 @@ __device__ __forceinline__ void run_positions(const Seg& g, uint32_t k, uint32_t
   }
 }
 
+// Cells with boundary links hand their velocity at the new time to the
+// link update before the next step, which would otherwise gather all Q
+// populations of the cell (one cache line each).  The velocity is taken
+// from the values as stored (stored(j): population j of cell k in the
+// storage format), decoded exactly as the link update would read them.
+// Only marked cells compute it, so the other cells pay one test.  WAVE: the
+// wavefront's cells are one wave of the mask (one cell per thread), so the
+// mask word is a scalar load.
+template <int Q, int ST, bool WAVE, class Stored>
+__device__ __forceinline__ void put_link_velocity(const Seg& g, uint32_t k, Stored&& stored) {
+  using SP = Store<ST>;
+  using R = typename SP::R;
+  if (!g.lmask) return;
+  const uint32_t w = WAVE ? __builtin_amdgcn_readfirstlane(k / kRunWave) : k / kRunWave;
+  const uint64_t m = gp(g.lmask)[w];
+  if (!((m >> (k & (kRunWave - 1))) & 1ull)) return;
+  const R isc = R(g.inv_scale);
+  R e[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) e[j] = SP::load(stored(j), R(Lattice<Q>::w(j)), isc);
+  R ux, uy, uz;
+  cell_velocity<Q, R>(e, g.F, ux, uy, uz);
+  LBM_GLOBAL R* v = gp(static_cast<R*>(g.lvel)) + 3 * (size_t)link_entry(m, gp(g.lwoff)[w], k);
+  v[0] = ux;
+  v[1] = uy;
+  v[2] = uz;
+}
+
 // One cell of an AA (or pull) step; `tile` is the workgroup's tile of the
-// launch and g the segment that owns it.
-template <int Q, int COLL, int ST, int MODE, int IDX>
+// launch and g the segment that owns it.  LV = false leaves out the
+// link-velocity epilogue (launches in which no solve has the buffer).
+template <int Q, int COLL, int ST, int MODE, int IDX, bool LV = true>
 __device__ __forceinline__ void aa_cell(const Seg& g, uint32_t tile) {
   constexpr bool GATHER = MODE != MODE_EVEN;
   using SP = Store<ST>;
@@ -174,12 +203,17 @@ __device__ __forceinline__ void aa_cell(const Seg& g, uint32_t tile) {
 #pragma unroll
       for (int i = 0; i < Q; ++i)
         st<LBM_NT_SCATTER>(SP::store(d[opp(i)], R(Lattice<Q>::w(i)), sc), pdf + pos[i]);
+      if constexpr (LV)
+        put_link_velocity<Q, ST, true>(
+            g, k, [&](int j) { return SP::store(d[j], R(Lattice<Q>::w(j)), sc); });
     } else {
       LBM_GLOBAL T* __restrict__ dst = gp(static_cast<T*>(g.dst));
 #pragma unroll
       for (int i = 0; i < Q; ++i)
         __builtin_nontemporal_store(SP::store(d[i], R(Lattice<Q>::w(i)), sc),
                                     dst + (size_t)i * S + k);
+      put_link_velocity<Q, ST, true>(
+          g, k, [&](int j) { return SP::store(d[j], R(Lattice<Q>::w(j)), sc); });
     }
   } else {
 #pragma unroll
@@ -191,14 +225,16 @@ __device__ __forceinline__ void aa_cell(const Seg& g, uint32_t tile) {
     for (int i = 0; i < Q; ++i)
       __builtin_nontemporal_store(SP::store(d[i], R(Lattice<Q>::w(i)), sc),
                                   pdf + (size_t)i * S + k);
+    put_link_velocity<Q, ST, true>(
+        g, k, [&](int j) { return SP::store(d[j], R(Lattice<Q>::w(j)), sc); });
   }
 }
 
-template <int Q, int COLL, int ST, int MODE, int IDX>
+template <int Q, int COLL, int ST, int MODE, int IDX, bool LV>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU))) void k_aa_step(const StepArgs a) {
   const uint32_t tile = xcd_tile(blockIdx.x, a.ntiles, a.xcd_remap);
-  with_seg(a, tile, [&](const Seg& g) { aa_cell<Q, COLL, ST, MODE, IDX>(g, tile); });
+  with_seg(a, tile, [&](const Seg& g) { aa_cell<Q, COLL, ST, MODE, IDX, LV>(g, tile); });
 }
 
 // Even step, two neighbouring cells per thread: every load and store moves a
@@ -240,6 +276,8 @@ __device__ __forceinline__ void even_pair_cells(const Seg& g, uint32_t tile) {
 #pragma unroll
   for (int j = 0; j < Q; ++j)
     __builtin_nontemporal_store(v[j], reinterpret_cast<LBM_GLOBAL T2*>(pdf + (size_t)j * S + k));
+  put_link_velocity<Q, ST, false>(g, k, [&](int j) { return v[j].x; });
+  put_link_velocity<Q, ST, false>(g, k + 1, [&](int j) { return v[j].y; });
 }
 
 template <int Q, int COLL, int ST>
@@ -318,6 +356,8 @@ __global__ __launch_bounds__(256) void k_odd_pipe(const StepArgs a) {
 #pragma unroll
         for (int i = 0; i < Q; ++i)
           st<LBM_NT_SCATTER>(SP::store(d[opp(i)], R(Lattice<Q>::w(i)), sc), pdf + pos[i]);
+        put_link_velocity<Q, ST, true>(
+            g, k, [&](int j) { return SP::store(d[j], R(Lattice<Q>::w(j)), sc); });
       }
     });
     if (!has_next) break;
@@ -330,10 +370,12 @@ __global__ __launch_bounds__(256) void k_odd_pipe(const StepArgs a) {
 
 // Host-side dispatch over (collision, storage, parity) for one Q.  `lds`:
 // dynamic LDS reserved per workgroup (the step kernels use none); it caps
-// how many workgroups share a CU.
+// how many workgroups share a CU.  links: some solve of the launch has a
+// link-velocity buffer (the odd kernel comes in a variant without the
+// epilogue; the others test for it at run time).
 template <int Q, int COLL, int ST>
 inline hipError_t launch_aa_cs(int mode, int idx, const StepArgs& a, int block, uint32_t lds,
-                               hipStream_t st) {
+                               bool links, hipStream_t st) {
   dim3 grid(a.ntiles), blk(block);
   if (mode == MODE_ODD_PIPE) {
     // resident workgroups of this kernel, rounded down to a multiple of 8
@@ -358,30 +400,43 @@ inline hipError_t launch_aa_cs(int mode, int idx, const StepArgs& a, int block, 
     hipLaunchKernelGGL((k_even_pair<Q, COLL, ST>), grid, blk, lds, st, a);
     return hipGetLastError();
   }
-  if (mode == MODE_ODD && idx == IDX_RUN)
-    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_ODD, IDX_RUN>), grid, blk, lds, st, a);
-  else if (mode == MODE_ODD && idx == IDX_16)
-    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_ODD, IDX_16>), grid, blk, lds, st, a);
-  else if (mode == MODE_ODD)
-    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_ODD, IDX_I32>), grid, blk, lds, st, a);
-  else if (mode == MODE_PULL && idx == IDX_16)
-    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_PULL, IDX_16>), grid, blk, lds, st, a);
-  else if (mode == MODE_PULL)
-    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_PULL, IDX_I32>), grid, blk, lds, st, a);
-  else
-    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_EVEN, IDX_I32>), grid, blk, lds, st, a);
+  if (mode == MODE_ODD && idx == IDX_RUN) {
+    if (links)
+      hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_ODD, IDX_RUN, true>), grid, blk, lds, st, a);
+    else
+      hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_ODD, IDX_RUN, false>), grid, blk, lds, st,
+                         a);
+  } else if (mode == MODE_ODD && idx == IDX_16) {
+    if (links)
+      hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_ODD, IDX_16, true>), grid, blk, lds, st, a);
+    else
+      hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_ODD, IDX_16, false>), grid, blk, lds, st, a);
+  } else if (mode == MODE_ODD) {
+    if (links)
+      hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_ODD, IDX_I32, true>), grid, blk, lds, st, a);
+    else
+      hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_ODD, IDX_I32, false>), grid, blk, lds, st,
+                         a);
+  } else if (mode == MODE_PULL && idx == IDX_16) {
+    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_PULL, IDX_16, true>), grid, blk, lds, st, a);
+  } else if (mode == MODE_PULL) {
+    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_PULL, IDX_I32, true>), grid, blk, lds, st, a);
+  } else {
+    hipLaunchKernelGGL((k_aa_step<Q, COLL, ST, MODE_EVEN, IDX_I32, true>), grid, blk, lds, st, a);
+  }
   return hipGetLastError();
 }
 
 template <int Q, int COLL>
 inline hipError_t launch_aa_c(int storage, int mode, int idx, const StepArgs& a, int block,
-                              uint32_t lds, hipStream_t st) {
+                              uint32_t lds, bool links, hipStream_t st) {
   switch (storage) {
-    case ST_F64: return launch_aa_cs<Q, COLL, ST_F64>(mode, idx, a, block, lds, st);
-    case ST_F32: return launch_aa_cs<Q, COLL, ST_F32>(mode, idx, a, block, lds, st);
-    case ST_F16DEV: return launch_aa_cs<Q, COLL, ST_F16DEV>(mode, idx, a, block, lds, st);
-    case ST_BF16DEV: return launch_aa_cs<Q, COLL, ST_BF16DEV>(mode, idx, a, block, lds, st);
-    case ST_F32DEV: return launch_aa_cs<Q, COLL, ST_F32DEV>(mode, idx, a, block, lds, st);
+    case ST_F64: return launch_aa_cs<Q, COLL, ST_F64>(mode, idx, a, block, lds, links, st);
+    case ST_F32: return launch_aa_cs<Q, COLL, ST_F32>(mode, idx, a, block, lds, links, st);
+    case ST_F16DEV: return launch_aa_cs<Q, COLL, ST_F16DEV>(mode, idx, a, block, lds, links, st);
+    case ST_BF16DEV:
+      return launch_aa_cs<Q, COLL, ST_BF16DEV>(mode, idx, a, block, lds, links, st);
+    case ST_F32DEV: return launch_aa_cs<Q, COLL, ST_F32DEV>(mode, idx, a, block, lds, links, st);
   }
   return hipErrorInvalidValue;
 }

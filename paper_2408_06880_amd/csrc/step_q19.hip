@@ -5,12 +5,12 @@
 namespace lbm {
 
 hipError_t launch_aa_q19(int coll, int storage, int mode, int idx, const StepArgs& a,
-                         int block, uint32_t lds, hipStream_t st) {
+                         int block, uint32_t lds, bool links, hipStream_t st) {
   switch (coll) {
-    case COLL_NONE: return launch_aa_c<19, COLL_NONE>(storage, mode, idx, a, block, lds, st);
-    case COLL_SRT: return launch_aa_c<19, COLL_SRT>(storage, mode, idx, a, block, lds, st);
-    case COLL_TRT: return launch_aa_c<19, COLL_TRT>(storage, mode, idx, a, block, lds, st);
-    case COLL_MRT: return launch_aa_c<19, COLL_MRT>(storage, mode, idx, a, block, lds, st);
+    case COLL_NONE: return launch_aa_c<19, COLL_NONE>(storage, mode, idx, a, block, lds, links, st);
+    case COLL_SRT: return launch_aa_c<19, COLL_SRT>(storage, mode, idx, a, block, lds, links, st);
+    case COLL_TRT: return launch_aa_c<19, COLL_TRT>(storage, mode, idx, a, block, lds, links, st);
+    case COLL_MRT: return launch_aa_c<19, COLL_MRT>(storage, mode, idx, a, block, lds, links, st);
   }
   return hipErrorInvalidValue;
 }

@@ -52,7 +52,8 @@ class lbm_layout(ctypes.Structure):
 
 class lbm_state(ctypes.Structure):
     _fields_ = [("layout", lbm_layout), ("storage", _i32), ("dev_exp", _i32), ("pdf", _vp),
-                ("index", _vp), ("index16", _vp), ("runs", _vp), ("links", _vp), ("t", _i64)]
+                ("index", _vp), ("index16", _vp), ("runs", _vp), ("links", _vp), ("t", _i64),
+                ("link_vel", _vp), ("link_vel_t", _i64)]
 
 
 class lbm_collision(ctypes.Structure):
@@ -104,6 +105,8 @@ _SIGS = {
     "lbm_compress_index": (_i32, [ctypes.POINTER(lbm_layout), _vp, _vp,
                                   ctypes.POINTER(_u64), _vp]),
     "lbm_runs_header_bytes": (_u64, [ctypes.POINTER(lbm_layout)]),
+    "lbm_link_vel_bytes": (_u64, [ctypes.POINTER(lbm_layout)]),
+    "lbm_link_vel_prepare": (_i32, [ctypes.POINTER(lbm_layout), _vp, _vp, _vp]),
     "lbm_compress_runs": (_i32, [ctypes.POINTER(lbm_layout), _vp, _vp, _u64,
                                  ctypes.POINTER(_u64), _vp]),
     "lbm_convert": (_i32, [ctypes.POINTER(lbm_state), ctypes.POINTER(lbm_state), _vp]),
@@ -223,6 +226,15 @@ def lbm_compress_index(layout, index, index16, stream=None):
 
 def lbm_runs_header_bytes(layout):
     return int(load().lbm_runs_header_bytes(ctypes.byref(layout)))
+
+
+def lbm_link_vel_bytes(layout):
+    return int(load().lbm_link_vel_bytes(ctypes.byref(layout)))
+
+
+def lbm_link_vel_prepare(layout, links, link_vel, stream=None):
+    _call("lbm_link_vel_prepare", ctypes.byref(layout), _ptr(links), _ptr(link_vel),
+          _stream(stream))
 
 
 def lbm_compress_runs(layout, index, runs, capacity, stream=None):
@@ -506,7 +518,11 @@ class SparseDomain:
 class Solver:
     """One sparse AA solve: PDF-list on the device plus its lbm_state."""
 
-    def __init__(self, domain: SparseDomain, storage=STORE_F32, dev_exp=0, device="cuda"):
+    def __init__(self, domain: SparseDomain, storage=STORE_F32, dev_exp=0, device="cuda",
+                 link_vel=True):
+        """link_vel: give a solve with boundary links its link-velocity
+        buffer (the step kernels then hand the outlet cells' velocity to
+        the next link update; same results, fewer gathers)."""
         import torch
         self.domain = domain
         n = domain.q * domain.stride
@@ -521,6 +537,13 @@ class Solver:
         st.runs = domain.runs.data_ptr() if domain.runs is not None else None
         st.links = domain.links.data_ptr() if domain.n_links else None
         st.t = 0
+        st.link_vel_t = -1
+        self.link_vel = None
+        nb = lbm_link_vel_bytes(domain.layout) if (link_vel and domain.n_links) else 0
+        if nb:
+            self.link_vel = torch.empty(nb, dtype=torch.uint8, device=device)
+            lbm_link_vel_prepare(domain.layout, domain.links, self.link_vel)
+            st.link_vel = self.link_vel.data_ptr()
         self.state = st
         self.storage = storage
         self._red_ws = torch.empty(lbm_reduce_workspace_bytes(domain.layout), dtype=torch.uint8,
@@ -539,7 +562,8 @@ class Solver:
     def converted(self, storage, dev_exp=0, stream=None):
         """A new Solver on the same domain holding this state in `storage`
         (same step count); this one is left unchanged."""
-        other = Solver(self.domain, storage, dev_exp, device=self.pdf.device)
+        other = Solver(self.domain, storage, dev_exp, device=self.pdf.device,
+                       link_vel=self.link_vel is not None)
         lbm_convert(self.state, other.state, stream)
         return other
 
@@ -610,10 +634,11 @@ class Solver:
         dst.copy_(torch.from_numpy(raw))
         torch.cuda.current_stream().synchronize()
         self.state.t = int(meta[-1])
+        self.state.link_vel_t = -1   # the PDF-list was written from the file
 
     def device_bytes(self):
         """Bytes of the device buffers this solver holds (not the domain's)."""
-        bufs = (self.pdf, self._red_ws, getattr(self, "_spare", None))
+        bufs = (self.pdf, self._red_ws, getattr(self, "_spare", None), self.link_vel)
         return sum(b.numel() * b.element_size() for b in bufs if b is not None)
 
 

@@ -27,12 +27,12 @@ def test_library_exports_every_declared_symbol():
     lib = lbm.load()
     for name in declared_functions():
         assert hasattr(lib, name), name
-    assert lbm.lbm_abi_version() == 6
+    assert lbm.lbm_abi_version() == 7
 
 
 def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(lbm.lbm_layout) == 56
-    assert ctypes.sizeof(lbm.lbm_state) == 56 + 8 + 40 + 8
+    assert ctypes.sizeof(lbm.lbm_state) == 56 + 8 + 40 + 8 + 16
     assert ctypes.sizeof(lbm.lbm_collision) == 8 + 8 * 6 + 8 * 4
     assert ctypes.sizeof(lbm.lbm_bspec) == 8 + 8 * 40
     assert ctypes.sizeof(lbm.lbm_reduction) == 48
@@ -55,6 +55,11 @@ def test_workspace_queries():
     assert lbm.lbm_runs_header_bytes(lay) == a256(4 * 17) + a256(8 * 16 * 18)
     lay.q, lay.stride = 27, 1000
     assert lbm.lbm_runs_header_bytes(lay) == a256(4 * 17) + a256(8 * 16 * 26)
+    # link-velocity buffer: mask word per wave, offsets (+1), 3 values of
+    # 8 bytes per link (an upper bound on the cells with links)
+    assert lbm.lbm_link_vel_bytes(lay) == 0
+    lay.n_links = 37
+    assert lbm.lbm_link_vel_bytes(lay) == a256(8 * 16) + a256(4 * 17) + a256(24 * 37)
 
 
 def _fake_state(q=19, nf=100, S=128, storage=lbm.STORE_F32):

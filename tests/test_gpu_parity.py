@@ -69,6 +69,7 @@ def _upload(sol, f_list, dev_exp):
         full[:, nf:] = pad_raw[:, :S - nf]
     sol.pdf.copy_(torch.from_numpy(full.reshape(-1)))
     sol.state.t = 0
+    sol.state.link_vel_t = -1
     return seen
 
 
@@ -1304,3 +1305,103 @@ def test_convert_storage_formats():
     other = lbm.SparseDomain(lab[:, :, 1:], 7, 19, lbm.ORDER_BLOCKED)
     with pytest.raises(lbm.LbmError):
         lbm.lbm_convert(a.state, lbm.Solver(other, lbm.STORE_F32).state)
+
+
+# ------------------------------------------------- link-velocity buffer
+def _link_vel_host(sol):
+    """(marked cells, velocities) held by a solve's link-velocity buffer."""
+    dom = sol.domain
+    q, S = dom.q, dom.stride
+    W = (S + 63) // 64
+    a256 = lambda v: (v + 255) // 256 * 256  # noqa: E731
+    raw = sol.link_vel.cpu().numpy()
+    mask = raw[:8 * W].view(np.uint64)
+    woff = raw[a256(8 * W):a256(8 * W) + 4 * (W + 1)].view(np.uint32)
+    bits = np.unpackbits(mask.view(np.uint8), bitorder="little").reshape(W, 64)
+    cells = np.nonzero(bits.reshape(-1))[0]
+    assert woff[W] == len(cells)
+    assert np.array_equal(woff[:W], np.concatenate([[0], np.cumsum(bits.sum(1))[:-1]]))
+    dt = np.float64 if sol.storage == lbm.STORE_F64 else np.float32
+    base = a256(8 * W) + a256(4 * (W + 1))
+    vel = raw[base:base + 3 * len(cells) * np.dtype(dt).itemsize].view(dt).reshape(-1, 3)
+    return cells, vel
+
+
+LINK_VEL_CASES = [(19, lbm.COLL_TRT, lbm.STORE_F64, "runs"),
+                  (19, lbm.COLL_TRT, lbm.STORE_F32, "i32"),
+                  (19, lbm.COLL_TRT, lbm.STORE_F16DEV, "runs"),
+                  (19, lbm.COLL_MRT, lbm.STORE_F32DEV, "i16"),
+                  (27, lbm.COLL_CUMULANT, lbm.STORE_F32, "runs"),
+                  (27, lbm.COLL_CUMULANT, lbm.STORE_BF16DEV, "i32"),
+                  (27, lbm.COLL_CM, lbm.STORE_F64, "i16")]
+
+
+@pytest.mark.parametrize("q,kind,storage,form", LINK_VEL_CASES)
+def test_link_velocity_buffer_is_bitwise_identical(q, kind, storage, form):
+    """With the link-velocity buffer the step kernels hand the boundary
+    cells' velocity to the next link update; the PDFs stay bit for bit those
+    of the gathering link update, over calls of 1 and several steps ending
+    at both parities, and the buffer holds the velocity of exactly the cells
+    that have links."""
+    _say("link vel", q, kind, storage, form)
+    lab = inputs.random_mask((19, 14, 23), 0.3, seed=5 * q + kind, n_classes=3,
+                             class_fraction=0.5)
+    coll, bs, _ = _params(q, kind, 0.7, (2e-5, -1e-5, 5e-6), CLASSES, omega_bulk=1.2)
+    dev_exp = 10 if storage in (lbm.STORE_F16DEV, lbm.STORE_BF16DEV) else 0
+    sols = []
+    for use in (False, True):
+        dom = lbm.SparseDomain(lab, 5, q, lbm.ORDER_BLOCKED)
+        if form == "runs":
+            dom.compact_runs()
+        elif form == "i16":
+            dom.compact()
+        torch.cuda.synchronize()
+        if not use:
+            _check_index(dom)
+        s = lbm.Solver(dom, storage, dev_exp, link_vel=use)
+        assert (s.link_vel is not None) == use and dom.n_links > 0
+        _upload(s, _random_state(q, dom.n_fluid, seed=q + kind, amp=1e-3), dev_exp)
+        sols.append(s)
+    ln = sols[1].domain.links[:2 * sols[1].domain.n_links].cpu().numpy().astype(np.int64)
+    _, _, opp = oracle.stencil(q)
+    S = sols[1].domain.stride
+    link_cells = np.unique(ln[0::2] - opp[ln[1::2] & 0xff] * S)
+    c, _, _ = oracle.stencil(q)
+    for n in (1, 5, 2, 9):
+        for s in sols:
+            s.step(n, coll, bs)
+        torch.cuda.synchronize()
+        assert torch.equal(sols[0].pdf, sols[1].pdf), (sols[1].t, n)
+        cells, vel = _link_vel_host(sols[1])
+        assert np.array_equal(cells, link_cells)
+        # written by the call's last step kernel: the velocity at sol.t
+        f = _download(sols[1], dev_exp)[:, cells]
+        u = (c.T.astype(float) @ f - 0.5 * np.array([2e-5, -1e-5, 5e-6])[:, None]) / f.sum(0)
+        tol = 1e-12 if storage == lbm.STORE_F64 else 1e-5
+        assert np.max(np.abs(vel.T - u)) <= tol * max(np.max(np.abs(u)), 1e-3)
+
+
+def test_link_velocity_buffer_batch_and_pull():
+    """Two vessel-tree solves advanced in one batch, each with its own
+    link-velocity buffer, and a pull-scheme solve: the same bits as without
+    the buffers."""
+    lab, per, _ = inputs.vessel_tree(n=40, r0=4.0, k_len=5.0, r_min=1.5, seed=4)
+    coll, bs, _ = _vessel_params()
+    out = []
+    for use in (False, True):
+        sols = []
+        for j in range(2):
+            dom = lbm.SparseDomain(lab, per, 27, lbm.ORDER_BLOCKED)
+            dom.compact_runs()
+            s = lbm.Solver(dom, lbm.STORE_F32, link_vel=use)
+            _upload(s, _random_state(27, dom.n_fluid, seed=40 + j, amp=1e-3), 0)
+            sols.append(s)
+        lbm.lbm_step_batch([s.state for s in sols], [coll, coll], [bs, bs], 7)
+        dom = lbm.SparseDomain(lab, per, 27, lbm.ORDER_BLOCKED)
+        p = lbm.Solver(dom, lbm.STORE_F32, link_vel=use)
+        _upload(p, _random_state(27, dom.n_fluid, seed=42, amp=1e-3), 0)
+        p.step_pull(8, coll, bs)
+        torch.cuda.synchronize()
+        out.append([s.pdf.clone() for s in sols] + [p.pdf.clone()])
+    for a, b in zip(*out):
+        assert torch.equal(a, b)
