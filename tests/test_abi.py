@@ -60,6 +60,14 @@ def test_workspace_queries():
     assert lbm.lbm_link_vel_bytes(lay) == 0
     lay.n_links = 37
     assert lbm.lbm_link_vel_bytes(lay) == a256(8 * 16) + a256(4 * 17) + a256(24 * 37)
+    # preparing the buffer checks its arguments before any device work; a
+    # layout without links needs no buffer
+    expect(lbm.LBM_EINVAL, lbm.lbm_link_vel_prepare, lay, None, 16, 0)
+    expect(lbm.LBM_EINVAL, lbm.lbm_link_vel_prepare, lay, 16, None, 0)
+    lay.q = 20
+    expect(lbm.LBM_EINVAL, lbm.lbm_link_vel_prepare, lay, 16, 16, 0)
+    lay.q, lay.n_links = 27, 0
+    lbm.lbm_link_vel_prepare(lay, None, None, 0)
 
 
 def _fake_state(q=19, nf=100, S=128, storage=lbm.STORE_F32):
