@@ -1341,8 +1341,8 @@ def test_link_velocity_buffer_is_bitwise_identical(q, kind, storage, form):
     """With the link-velocity buffer the step kernels hand the boundary
     cells' velocity to the next link update; the PDFs stay bit for bit those
     of the gathering link update, over calls of 1 and several steps ending
-    at both parities, and the buffer holds the velocity of exactly the cells
-    that have links."""
+    at both parities and after a PDF-list written from outside, and the
+    buffer holds the velocity of exactly the cells that have links."""
     _say("link vel", q, kind, storage, form)
     lab = inputs.random_mask((19, 14, 23), 0.3, seed=5 * q + kind, n_classes=3,
                              class_fraction=0.5)
@@ -1379,6 +1379,12 @@ def test_link_velocity_buffer_is_bitwise_identical(q, kind, storage, form):
         u = (c.T.astype(float) @ f - 0.5 * np.array([2e-5, -1e-5, 5e-6])[:, None]) / f.sum(0)
         tol = 1e-12 if storage == lbm.STORE_F64 else 1e-5
         assert np.max(np.abs(vel.T - u)) <= tol * max(np.max(np.abs(u)), 1e-3)
+    # a PDF-list written from outside clears the stamp: the next step gathers
+    for s in sols:
+        _upload(s, _random_state(q, s.domain.n_fluid, seed=7 * q + kind, amp=1e-3), dev_exp)
+        s.step(3, coll, bs)
+    torch.cuda.synchronize()
+    assert torch.equal(sols[0].pdf, sols[1].pdf)
 
 
 def test_link_velocity_buffer_batch_and_pull():
