@@ -265,9 +265,10 @@ lbm_status lbm_compress_runs(const lbm_layout* layout, const int32_t* index, voi
  * states it needs the velocity of each cell that has an outlet link before
  * every step; without the buffer the link update gathers all q populations
  * of such a cell (one cache line each).  With it, every step kernel also
- * writes the velocity of the cells that have links, the step calls set
- * lbm_state.link_vel_t = t after each step, and a link update at time t
- * reads the velocities there when link_vel_t == t (else it gathers).
+ * writes the density and momentum sums of the cells that have links, the
+ * step calls set lbm_state.link_vel_t = t after each step, and a link
+ * update at time t forms the velocities from those sums (with the force
+ * of the step it precedes) when link_vel_t == t, else it gathers.
  * lbm_init_equilibrium and lbm_convert set link_vel_t = -1 on the state
  * they write; a caller that writes a PDF-list by other means (an upload, a
  * restored checkpoint) sets it to -1 too.  Results are bitwise the same

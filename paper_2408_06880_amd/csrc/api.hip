@@ -246,7 +246,7 @@ LinkVelView link_vel_view(const lbm_layout& L, void* p) {
   v.nw = (uint32_t)(((uint64_t)L.stride + kRunWave - 1) / kRunWave);
   const uint64_t mask_b = align256(8 * (uint64_t)v.nw);
   const uint64_t woff_b = align256(4 * ((uint64_t)v.nw + 1));
-  v.bytes = mask_b + woff_b + align256(3 * 8 * (uint64_t)L.n_links);
+  v.bytes = mask_b + woff_b + align256(4 * 8 * (uint64_t)L.n_links);
   v.mask = nullptr;
   v.woff = nullptr;
   v.vel = nullptr;

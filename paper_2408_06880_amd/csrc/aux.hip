@@ -208,7 +208,9 @@ __global__ __launch_bounds__(256) void k_links(const LinkArgs a) {
   if (pressure) {
     R d[Q];
     gather_post<Q, ST, ODD_T>(a.g, k, d);
-    cell_velocity<Q, R>(d, a.g.F, ux, uy, uz);
+    R sums[4];
+    cell_sums<Q, R>(d, sums);
+    sums_velocity<R>(sums, a.g.F, ux, uy, uz);
   }
 #pragma unroll
   for (int m = 0; m < Q - 1; ++m)
@@ -216,9 +218,10 @@ __global__ __launch_bounds__(256) void k_links(const LinkArgs a) {
       pdf[pos[m]] = link_slot<Q, ST>(a, meta[m], v[m], ux, uy, uz);
 }
 
-// The same update when the step kernel before it left the velocity of every
-// cell with links in the link-velocity buffer: no thread reads a slot that
-// another one writes, so one thread takes one link.
+// The same update when the step kernel before it left the density and
+// momentum sums of every cell with links in the link-velocity buffer: no
+// thread reads a slot that another one writes, so one thread takes one
+// link.
 template <int Q, int ST>
 __global__ __launch_bounds__(256) void k_links_vel(const LinkArgs a) {
   using SP = Store<ST>;
@@ -236,11 +239,10 @@ __global__ __launch_bounds__(256) void k_links_vel(const LinkArgs a) {
   if (type == 2) {
     const uint32_t k = pos - (uint32_t)opp(meta & 0xff) * a.g.S;
     const uint32_t w = k / kRunWave;
-    const LBM_GLOBAL R* u = gp(static_cast<const R*>(a.g.lvel)) +
-                            3 * (size_t)link_entry(gp(a.g.lmask)[w], gp(a.g.lwoff)[w], k);
-    ux = u[0];
-    uy = u[1];
-    uz = u[2];
+    const LBM_GLOBAL R* p = gp(static_cast<const R*>(a.g.lvel)) +
+                            4 * (size_t)link_entry(gp(a.g.lmask)[w], gp(a.g.lwoff)[w], k);
+    const R sums[4] = {p[0], p[1], p[2], p[3]};
+    sums_velocity<R>(sums, a.g.F, ux, uy, uz);
   }
   pdf[pos] = link_slot<Q, ST>(a, meta, v, ux, uy, uz);
 }

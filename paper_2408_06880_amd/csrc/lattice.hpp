@@ -106,12 +106,12 @@ struct Store<ST_BF16DEV> {
 
 // Velocity of a cell from its post-collision deviations d (natural order) at
 // the current time, for the pressure outlet's anti-bounce-back: the
-// half-force velocity u = (sum_i c_i d_i - F/2) / rho.  The link update and
-// the step kernels that hand it on both use this one expression, so the two
-// routes give the same bits.
+// half-force velocity u = (sum_i c_i d_i - F/2) / rho, in two parts: the
+// sums m = (rho - 1, j) and the velocity from them.  The link update and
+// the step kernels that hand the sums on use these same expressions, so the
+// two routes give the same bits (the force is that of the step taken).
 template <int Q, class R>
-__device__ __forceinline__ void cell_velocity(const R (&d)[Q], const double (&F)[3], R& ux,
-                                              R& uy, R& uz) {
+__device__ __forceinline__ void cell_sums(const R (&d)[Q], R (&m)[4]) {
   R drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
@@ -120,10 +120,19 @@ __device__ __forceinline__ void cell_velocity(const R (&d)[Q], const double (&F)
     jy += R(Lattice<Q>::cy[j]) * d[j];
     jz += R(Lattice<Q>::cz[j]) * d[j];
   }
-  const R r = R(1) + drho;
-  ux = (jx - R(0.5) * R(F[0])) / r;
-  uy = (jy - R(0.5) * R(F[1])) / r;
-  uz = (jz - R(0.5) * R(F[2])) / r;
+  m[0] = drho;
+  m[1] = jx;
+  m[2] = jy;
+  m[3] = jz;
+}
+
+template <class R>
+__device__ __forceinline__ void sums_velocity(const R (&m)[4], const double (&F)[3], R& ux,
+                                              R& uy, R& uz) {
+  const R r = R(1) + m[0];
+  ux = (m[1] - R(0.5) * R(F[0])) / r;
+  uy = (m[2] - R(0.5) * R(F[1])) / r;
+  uz = (m[3] - R(0.5) * R(F[2])) / r;
 }
 
 // ---------------------------------------------------------------------------
@@ -151,9 +160,9 @@ constexpr uint32_t kRunWave = 64;
 
 // Link-velocity buffer of a solve with boundary links (parts 256-byte
 // aligned): uint64 mask[W] (bit l of wave w: cell 64w + l has a link),
-// uint32 woff[W + 1] (exclusive prefix of the mask popcounts), then three
-// values of the compute type per marked cell, in list order (8 bytes per
-// value reserved).  Entry of cell k: woff[k/64] + popcount of the mask bits
+// uint32 woff[W + 1] (exclusive prefix of the mask popcounts), then four
+// values of the compute type per marked cell, in list order: its sums
+// (rho - 1, j) at the current time (8 bytes per value reserved).  Entry of cell k: woff[k/64] + popcount of the mask bits
 // below k % 64.
 __device__ __forceinline__ uint32_t link_entry(uint64_t m, uint32_t woff, uint32_t k) {
   const uint32_t b = k & (kRunWave - 1);
@@ -171,7 +180,7 @@ struct Seg {
   const int32_t* rval;     // run form: run values
   const uint64_t* lmask;   // link velocities: cells with links, bit per lane [wave]
   const uint32_t* lwoff;   // link velocities: first entry of each wave
-  void* lvel;              // link velocities: 3 values of the compute type per entry
+  void* lvel;              // link velocities: 4 sums (compute type) per entry
   uint32_t ntiles16;       // tiles of the compact index-list
   uint32_t S;              // stride
   uint32_t nf;             // fluid cells

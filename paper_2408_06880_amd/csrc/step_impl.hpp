@@ -113,11 +113,12 @@ __device__ __forceinline__ void run_positions(const Seg& g, uint32_t k, uint32_t
   }
 }
 
-// Cells with boundary links hand their velocity at the new time to the
-// link update before the next step, which would otherwise gather all Q
-// populations of the cell (one cache line each).  The velocity is taken
-// from the values as stored (stored(j): population j of cell k in the
-// storage format), decoded exactly as the link update would read them.
+// Cells with boundary links hand their density and momentum sums at the
+// new time to the link update before the next step, which would otherwise
+// gather all Q populations of the cell (one cache line each) to form the
+// velocity.  The sums are taken from the values as stored (stored(j):
+// population j of cell k in the storage format), decoded exactly as the
+// link update would read them.
 // Only marked cells compute it, so the other cells pay one test.  WAVE: the
 // wavefront's cells are one wave of the mask (one cell per thread), so the
 // mask word is a scalar load.
@@ -133,12 +134,11 @@ __device__ __forceinline__ void put_link_velocity(const Seg& g, uint32_t k, Stor
   R e[Q];
 #pragma unroll
   for (int j = 0; j < Q; ++j) e[j] = SP::load(stored(j), R(Lattice<Q>::w(j)), isc);
-  R ux, uy, uz;
-  cell_velocity<Q, R>(e, g.F, ux, uy, uz);
-  LBM_GLOBAL R* v = gp(static_cast<R*>(g.lvel)) + 3 * (size_t)link_entry(m, gp(g.lwoff)[w], k);
-  v[0] = ux;
-  v[1] = uy;
-  v[2] = uz;
+  R sums[4];
+  cell_sums<Q, R>(e, sums);
+  LBM_GLOBAL R* v = gp(static_cast<R*>(g.lvel)) + 4 * (size_t)link_entry(m, gp(g.lwoff)[w], k);
+#pragma unroll
+  for (int a = 0; a < 4; ++a) v[a] = sums[a];
 }
 
 // One cell of an AA (or pull) step; `tile` is the workgroup's tile of the

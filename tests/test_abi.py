@@ -55,11 +55,11 @@ def test_workspace_queries():
     assert lbm.lbm_runs_header_bytes(lay) == a256(4 * 17) + a256(8 * 16 * 18)
     lay.q, lay.stride = 27, 1000
     assert lbm.lbm_runs_header_bytes(lay) == a256(4 * 17) + a256(8 * 16 * 26)
-    # link-velocity buffer: mask word per wave, offsets (+1), 3 values of
+    # link-velocity buffer: mask word per wave, offsets (+1), 4 values of
     # 8 bytes per link (an upper bound on the cells with links)
     assert lbm.lbm_link_vel_bytes(lay) == 0
     lay.n_links = 37
-    assert lbm.lbm_link_vel_bytes(lay) == a256(8 * 16) + a256(4 * 17) + a256(24 * 37)
+    assert lbm.lbm_link_vel_bytes(lay) == a256(8 * 16) + a256(4 * 17) + a256(32 * 37)
     # preparing the buffer checks its arguments before any device work; a
     # layout without links needs no buffer
     expect(lbm.LBM_EINVAL, lbm.lbm_link_vel_prepare, lay, None, 16, 0)

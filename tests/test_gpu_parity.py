@@ -1309,7 +1309,8 @@ def test_convert_storage_formats():
 
 # ------------------------------------------------- link-velocity buffer
 def _link_vel_host(sol):
-    """(marked cells, velocities) held by a solve's link-velocity buffer."""
+    """(marked cells, sums (rho - 1, j)) held by a solve's link-velocity
+    buffer."""
     dom = sol.domain
     q, S = dom.q, dom.stride
     W = (S + 63) // 64
@@ -1323,8 +1324,8 @@ def _link_vel_host(sol):
     assert np.array_equal(woff[:W], np.concatenate([[0], np.cumsum(bits.sum(1))[:-1]]))
     dt = np.float64 if sol.storage == lbm.STORE_F64 else np.float32
     base = a256(8 * W) + a256(4 * (W + 1))
-    vel = raw[base:base + 3 * len(cells) * np.dtype(dt).itemsize].view(dt).reshape(-1, 3)
-    return cells, vel
+    sums = raw[base:base + 4 * len(cells) * np.dtype(dt).itemsize].view(dt).reshape(-1, 4)
+    return cells, sums
 
 
 LINK_VEL_CASES = [(19, lbm.COLL_TRT, lbm.STORE_F64, "runs"),
@@ -1339,14 +1340,16 @@ LINK_VEL_CASES = [(19, lbm.COLL_TRT, lbm.STORE_F64, "runs"),
 @pytest.mark.parametrize("q,kind,storage,form", LINK_VEL_CASES)
 def test_link_velocity_buffer_is_bitwise_identical(q, kind, storage, form):
     """With the link-velocity buffer the step kernels hand the boundary
-    cells' velocity to the next link update; the PDFs stay bit for bit those
-    of the gathering link update, over calls of 1 and several steps ending
-    at both parities and after a PDF-list written from outside, and the
-    buffer holds the velocity of exactly the cells that have links."""
+    cells' density and momentum to the next link update; the PDFs stay bit
+    for bit those of the gathering link update, over calls of 1 and several
+    steps ending at both parities, a force that changes between calls and a
+    PDF-list written from outside, and the buffer holds the sums of exactly
+    the cells that have links."""
     _say("link vel", q, kind, storage, form)
     lab = inputs.random_mask((19, 14, 23), 0.3, seed=5 * q + kind, n_classes=3,
                              class_fraction=0.5)
     coll, bs, _ = _params(q, kind, 0.7, (2e-5, -1e-5, 5e-6), CLASSES, omega_bulk=1.2)
+    coll2, _, _ = _params(q, kind, 0.7, (-3e-5, 2e-5, 1e-5), CLASSES, omega_bulk=1.2)
     dev_exp = 10 if storage in (lbm.STORE_F16DEV, lbm.STORE_BF16DEV) else 0
     sols = []
     for use in (False, True):
@@ -1367,18 +1370,18 @@ def test_link_velocity_buffer_is_bitwise_identical(q, kind, storage, form):
     S = sols[1].domain.stride
     link_cells = np.unique(ln[0::2] - opp[ln[1::2] & 0xff] * S)
     c, _, _ = oracle.stencil(q)
-    for n in (1, 5, 2, 9):
+    for n, cl in ((1, coll), (5, coll), (2, coll2), (9, coll)):
         for s in sols:
-            s.step(n, coll, bs)
+            s.step(n, cl, bs)
         torch.cuda.synchronize()
         assert torch.equal(sols[0].pdf, sols[1].pdf), (sols[1].t, n)
-        cells, vel = _link_vel_host(sols[1])
+        cells, sums = _link_vel_host(sols[1])
         assert np.array_equal(cells, link_cells)
-        # written by the call's last step kernel: the velocity at sol.t
+        # written by the call's last step kernel: the sums at sol.t
         f = _download(sols[1], dev_exp)[:, cells]
-        u = (c.T.astype(float) @ f - 0.5 * np.array([2e-5, -1e-5, 5e-6])[:, None]) / f.sum(0)
+        ref = np.vstack([f.sum(0) - 1.0, c.T.astype(float) @ f])
         tol = 1e-12 if storage == lbm.STORE_F64 else 1e-5
-        assert np.max(np.abs(vel.T - u)) <= tol * max(np.max(np.abs(u)), 1e-3)
+        assert np.max(np.abs(sums.T - ref)) <= tol * max(np.max(np.abs(ref)), 1e-3)
     # a PDF-list written from outside clears the stamp: the next step gathers
     for s in sols:
         _upload(s, _random_state(q, s.domain.n_fluid, seed=7 * q + kind, amp=1e-3), dev_exp)
