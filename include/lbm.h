@@ -469,7 +469,8 @@ typedef struct {
  * now on, process-wide (e.g. from an autotuner cache).  Changing it does
  * not change results except through workgroup-to-tile assignment, which
  * the arithmetic does not depend on.  Defaults (measured on MI355X): block
- * 256; XCD-aware tile order (chunks of 16 tiles) for the odd kernel only;
+ * 256; XCD-aware tile order for the odd kernel only (chunks of 16 tiles,
+ * 256 for D3Q19 in 16-bit storage);
  * two cells per thread for even steps in 16-bit storage; D3Q19 FP32 and
  * FP32-dev at most 4
  * (odd) and 3 (even) workgroups per CU; D3Q19 FP64 even steps with block

@@ -16,7 +16,7 @@ import math
 import os
 
 BLOCKS = (64, 128, 256)
-XCD = (0, 1, 16)        # dispatch order, one eighth per XCD, chunks of 16 tiles
+XCD = (0, 1, 16, 256)   # dispatch order, one eighth per XCD, chunks of 16 / 256 tiles
 CELLS = (1, 2)          # cells per thread, even-step kernel only
 GROUPS = (0, 2, 3, 4)   # resident workgroups per CU (0: as registers allow)
 KERNEL_NAMES = {0: "odd", 1: "even", 2: "dense"}

@@ -66,8 +66,10 @@ void launch_defaults() {
         c.block = 256;
         // odd step: chunks of 16 tiles dealt round-robin to the XCDs
         // (FP64 638 -> 618 us, FP32 357 -> 342 us against one contiguous
-        // eighth per XCD; chunks of 12-32 tiles measure the same)
-        c.xcd_remap = (k == LBM_KERNEL_ODD) ? 16 : 0;
+        // eighth per XCD; chunks of 12-32 tiles measure the same); D3Q19
+        // 16-bit storage: chunks of 256 (FP16-dev 230.0 -> 227.7 us,
+        // BF16-dev 232.4 -> 229.6 us against 16)
+        c.xcd_remap = (k == LBM_KERNEL_ODD) ? ((qi == 0 && is16(st)) ? 256 : 16) : 0;
         c.pipelined = 0;
         c.cells_per_thread = (k == LBM_KERNEL_EVEN && is16(st)) ? 2 : 1;
         c.max_groups_per_cu = 0;

@@ -200,6 +200,9 @@ def test_launch_table_roundtrip():
     assert lbm.lbm_get_launch(lbm.KERNEL_ODD, 19, lbm.STORE_F64, full=True) == (256, 16, 0, 1, 0)
     assert lbm.lbm_get_launch(lbm.KERNEL_EVEN, 19, lbm.STORE_F32DEV, full=True) == (256, 0, 0, 1, 3)
     assert lbm.lbm_get_launch(lbm.KERNEL_ODD, 27, lbm.STORE_F32, full=True) == (256, 16, 0, 1, 3)
+    # D3Q19 16-bit storage: the odd step's tiles in chunks of 256
+    assert lbm.lbm_get_launch(lbm.KERNEL_ODD, 19, lbm.STORE_F16DEV, full=True) == (256, 256, 0, 1, 0)
+    assert lbm.lbm_get_launch(lbm.KERNEL_ODD, 27, lbm.STORE_F16DEV, full=True) == (256, 16, 0, 1, 0)
     assert lbm.lbm_get_launch(lbm.KERNEL_DENSE, 19, lbm.STORE_F32, full=True)[4] == 0
     lbm.lbm_set_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F16DEV, 128, 0)
     assert lbm.lbm_get_launch(lbm.KERNEL_EVEN, 27, lbm.STORE_F16DEV) == (128, 0)

@@ -73,7 +73,7 @@ def test_tuner_installs_a_measured_configuration(tmp_path):
     try:
         path = str(tmp_path / "launch.json")
         res = autotune.tune_solver(sol, coll, cache_path=path, steps=3)
-        for k, n in ((0, 36), (1, 72)):
+        for k, n in ((0, 48), (1, 96)):
             (b, x, c, g), timings = res[k]
             assert len(timings) == n and min(timings.values()) == timings[(b, x, c, g)]
             got = lbm.lbm_get_launch(k, 19, lbm.STORE_F32, full=True)

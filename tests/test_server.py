@@ -93,9 +93,9 @@ def test_tuner_choice_and_cache(tmp_path):
     assert autotune.choose({(256, 1, 1, 3): 1.0, (256, 1, 1, 0): 1.0}) == (256, 1, 1, 0)
     res = autotune.tune(lambda k, b, x, c, g: 1.0 / b + (0.1 if x == 0 else 0.0) + k
                         - (0.01 if c == 2 else 0.0) - (0.001 if g == 3 else 0.0))
-    # tile orders 1 and 16 tie here: the larger value (chunks of 16) is kept
-    assert res[0][0] == (256, 16, 1, 3) and res[1][0] == (256, 16, 2, 3)
-    assert len(res[0][1]) == 36 and len(res[1][1]) == 72     # cells per thread: even only
+    # tile orders 1, 16 and 256 tie here: the largest value is kept
+    assert res[0][0] == (256, 256, 1, 3) and res[1][0] == (256, 256, 2, 3)
+    assert len(res[0][1]) == 48 and len(res[1][1]) == 96     # cells per thread: even only
     path = tmp_path / "launch.json"
     autotune.save(str(path), {autotune.cache_key("gfx950", 0, 19, 1, 23): {"block": 128,
                                                                             "xcd_remap": 1}})
