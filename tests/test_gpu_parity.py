@@ -1328,24 +1328,26 @@ def _link_vel_host(sol):
     return cells, sums
 
 
-LINK_VEL_CASES = [(19, lbm.COLL_TRT, lbm.STORE_F64, "runs"),
-                  (19, lbm.COLL_TRT, lbm.STORE_F32, "i32"),
-                  (19, lbm.COLL_TRT, lbm.STORE_F16DEV, "runs"),
-                  (19, lbm.COLL_MRT, lbm.STORE_F32DEV, "i16"),
-                  (27, lbm.COLL_CUMULANT, lbm.STORE_F32, "runs"),
-                  (27, lbm.COLL_CUMULANT, lbm.STORE_BF16DEV, "i32"),
-                  (27, lbm.COLL_CM, lbm.STORE_F64, "i16")]
+LINK_VEL_CASES = [(19, lbm.COLL_TRT, lbm.STORE_F64, "runs", 64),
+                  (19, lbm.COLL_TRT, lbm.STORE_F64, "runs", 1),
+                  (19, lbm.COLL_TRT, lbm.STORE_F32, "i32", 64),
+                  (19, lbm.COLL_TRT, lbm.STORE_F16DEV, "runs", 64),
+                  (19, lbm.COLL_TRT, lbm.STORE_F16DEV, "i32", 1),
+                  (19, lbm.COLL_MRT, lbm.STORE_F32DEV, "i16", 64),
+                  (27, lbm.COLL_CUMULANT, lbm.STORE_F32, "runs", 64),
+                  (27, lbm.COLL_CUMULANT, lbm.STORE_BF16DEV, "i32", 64),
+                  (27, lbm.COLL_CM, lbm.STORE_F64, "i16", 64)]
 
 
-@pytest.mark.parametrize("q,kind,storage,form", LINK_VEL_CASES)
-def test_link_velocity_buffer_is_bitwise_identical(q, kind, storage, form):
+@pytest.mark.parametrize("q,kind,storage,form,align", LINK_VEL_CASES)
+def test_link_velocity_buffer_is_bitwise_identical(q, kind, storage, form, align):
     """With the link-velocity buffer the step kernels hand the boundary
     cells' density and momentum to the next link update; the PDFs stay bit
     for bit those of the gathering link update, over calls of 1 and several
     steps ending at both parities, a force that changes between calls and a
     PDF-list written from outside, and the buffer holds the sums of exactly
     the cells that have links."""
-    _say("link vel", q, kind, storage, form)
+    _say("link vel", q, kind, storage, form, align)
     lab = inputs.random_mask((19, 14, 23), 0.3, seed=5 * q + kind, n_classes=3,
                              class_fraction=0.5)
     coll, bs, _ = _params(q, kind, 0.7, (2e-5, -1e-5, 5e-6), CLASSES, omega_bulk=1.2)
@@ -1353,7 +1355,7 @@ def test_link_velocity_buffer_is_bitwise_identical(q, kind, storage, form):
     dev_exp = 10 if storage in (lbm.STORE_F16DEV, lbm.STORE_BF16DEV) else 0
     sols = []
     for use in (False, True):
-        dom = lbm.SparseDomain(lab, 5, q, lbm.ORDER_BLOCKED)
+        dom = lbm.SparseDomain(lab, 5, q, lbm.ORDER_BLOCKED, align=align)
         if form == "runs":
             dom.compact_runs()
         elif form == "i16":
