@@ -431,6 +431,39 @@ def test_full_size_packing_two_steps_fp32(packing256, order, form):
         assert np.max(np.abs(got - ref) / ref) <= 1e-5
 
 
+def test_full_size_packing_d3q27_cumulant_two_steps(packing256):
+    """The D3Q27 cumulant kernels on the 256^3 packing at porosity 0.6
+    (10.06 M fluid cells, FP32, blocked order, run-compressed index, default
+    launch table; the configuration of the D3Q27 profile): one odd and one
+    even step from a perturbed state match the oracle's sparse AA scheme on
+    every fluid cell."""
+    lab, per, info, _ = packing256
+    q = 27
+    _say("full size D3Q27 cumulant two steps", info["n_fluid"])
+    ref_lay = oracle.sparse_build(lab, per, q, order=lbm.ORDER_BLOCKED, align=64)
+    coll, _, op = _params(q, lbm.COLL_CUMULANT, 0.8, (1e-6, 0, 0), [])
+    dom = lbm.SparseDomain(lab, per, q, lbm.ORDER_BLOCKED)
+    dom.compact_runs()
+    torch.cuda.synchronize()
+    assert np.array_equal(ref_lay.cells, dom.cells[:dom.n_fluid].cpu().numpy())
+    sol = lbm.Solver(dom, lbm.STORE_F32)
+    seen = _upload(sol, _random_state(q, dom.n_fluid, seed=23, amp=1e-3), 0)
+    S, nf = ref_lay.stride, dom.n_fluid
+    pdf = np.zeros(q * S)
+    for i in range(q):
+        pdf[i * S:i * S + nf] = seen[i]
+    del seen
+    for t in range(2):
+        sol.step(1, coll)
+        pdf = oracle.sparse_run(op, ref_lay, pdf, t, 1)
+        torch.cuda.synchronize()
+        got = _download(sol, 0)
+        ref = oracle.sparse_gather(ref_lay, pdf, t + 1)
+        err = float(np.max(np.abs(got - ref) / np.abs(ref)))
+        _say("full size D3Q27 step", t + 1, "max rel err", err)
+        assert err <= 1e-5
+
+
 def test_full_size_packing_fp64_100_steps(packing256):
     """The benchmark's headline configuration, exactly as bench.py times it:
     256^3 packing at porosity 0.6 (10.06 M fluid cells), D3Q19 TRT FP64,
