@@ -464,6 +464,42 @@ def test_full_size_packing_d3q27_cumulant_two_steps(packing256):
         assert err <= 1e-5
 
 
+@pytest.mark.parametrize("storage", [lbm.STORE_F64, lbm.STORE_F16DEV])
+def test_full_size_tile_orders_bitwise(packing256, storage):
+    """On the 256^3 benchmark packing (about 39 000 odd-step tiles, so
+    every chunk size has full rounds and a partial last round) the odd and
+    even steps give
+    the same bits in dispatch order, one eighth per XCD, and chunks of 16
+    and 256 tiles: each order assigns every tile to exactly one
+    workgroup."""
+    lab, per, info, _ = packing256
+    _say("full size tile orders", storage)
+    coll = lbm.collision(lbm.COLL_TRT, tau=0.8, force=(1e-6, 0, 0))
+    dev_exp = 14 if storage == lbm.STORE_F16DEV else 0
+    dom = lbm.SparseDomain(lab, per, 19, lbm.ORDER_BLOCKED)
+    dom.compact_runs()
+    f0 = _random_state(19, dom.n_fluid, seed=29, amp=1e-3)
+    old = [lbm.lbm_get_launch(k, 19, storage, full=True) for k in (0, 1)]
+    ref = None
+    try:
+        for x in (0, 1, 16, 256):
+            for k in (0, 1):
+                b0, _, p0, c0, g0 = old[k]
+                lbm.lbm_set_launch(k, 19, storage, b0, x, p0, c0, g0)
+            s = lbm.Solver(dom, storage, dev_exp)
+            _upload(s, f0, dev_exp)
+            s.step(2, coll)
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = s.pdf.clone()
+            else:
+                assert torch.equal(ref, s.pdf), x
+            del s
+    finally:
+        for k in (0, 1):
+            lbm.lbm_set_launch(k, 19, storage, *old[k])
+
+
 def test_full_size_packing_fp64_100_steps(packing256):
     """The benchmark's headline configuration, exactly as bench.py times it:
     256^3 packing at porosity 0.6 (10.06 M fluid cells), D3Q19 TRT FP64,
